@@ -1,0 +1,174 @@
+/* clak.h — C ABI of the MI355X CLAK-Eig library (libclak.so).
+ *
+ * The library solves the two-dimensional grid of generalised least-squares
+ * problems of the supplementary notes (section 1, equation probDef): for every
+ * SNP i and trait j
+ *
+ *     b_ij   = (X_i^T M_j^{-1} X_i)^{-1} X_i^T M_j^{-1} y_j,
+ *     M_j    = s2_j (h2_j Phi + (1 - h2_j) I),   X_i = [X_L | g_i],
+ *
+ * by the multi-trait CLAK-Eig algorithm (section 3, the CLAK-Eig listing for
+ * multi-trait analysis): Phi = Z W Z^T is eigendecomposed once, X_L, the SNP
+ * columns and Y are rotated by Z^T, and every (SNP, trait) cell reduces to
+ * diagonal-weighted sums over the n individuals plus a Schur-complement solve
+ * of the partitioned p x p system S b = [b_T ; W_R^T Y_j] (p = p_L + 1).
+ *
+ * Conventions
+ *   - Every pointer argument named d_* is a DEVICE pointer on the device that
+ *     was current when the plan was created.  All matrices are column-major
+ *     with an explicit leading dimension; all sizes are int64_t.
+ *   - The caller owns every buffer it passes in (inputs, outputs and the
+ *     workspace).  The library owns only the opaque plan (host memory plus a
+ *     rocBLAS handle), released by clak_plan_destroy.  It never frees caller
+ *     memory.
+ *   - No C++ exception and no abort crosses the ABI: every entry point returns
+ *     a clak_status and, on failure, sets a thread-local message readable with
+ *     clak_last_error().
+ *   - Host-side argument checks (sizes, leading dimensions, null pointers,
+ *     call order) run before any device work.  Checks that need device data
+ *     (h2 range, s2 > 0, positive definiteness) run on the device inside the
+ *     synchronous set-up calls, which report them through their status.
+ *   - clak_run_block is asynchronous on the plan's stream.  A device fault
+ *     surfaces at the next synchronising call.
+ *
+ * Call order for one cohort
+ *   clak_plan_create -> clak_plan_workspace_size -> clak_plan_set_workspace
+ *   [-> clak_plan_set_stream] -> clak_set_kinship | clak_set_eigen
+ *   -> clak_set_covariates -> clak_set_traits -> clak_run_block (any number of
+ *   times) -> clak_plan_destroy.
+ *   clak_set_traits may be repeated (new phenotypes, same kinship and
+ *   covariates); clak_set_covariates may be repeated (it invalidates the
+ *   traits); clak_set_kinship/clak_set_eigen may be repeated (it invalidates
+ *   covariates and traits).  Any other order returns CLAK_E_STATE.
+ */
+#ifndef CLAK_H
+#define CLAK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum clak_status {
+  CLAK_OK = 0,
+  CLAK_E_ARG = 1,           /* bad size, leading dimension, null pointer, NaN/Inf, h2 outside [0,1], s2 <= 0 */
+  CLAK_E_STATE = 2,         /* call out of order */
+  CLAK_E_NOT_SPD = 3,       /* some h2_j w_k + 1 - h2_j <= 0: M_j not positive definite */
+  CLAK_E_COV_SINGULAR = 4,  /* X_L rank deficient, or X_L^T M_j^{-1} X_L not positive definite */
+  CLAK_E_EIG = 5,           /* the eigensolver did not converge */
+  CLAK_E_WORKSPACE = 6,     /* workspace missing, too small or misaligned */
+  CLAK_E_DEVICE = 7,        /* HIP or rocSOLVER failure */
+  CLAK_E_UNSUPPORTED = 8    /* size beyond what the chosen precision supports */
+} clak_status;
+
+/* Arithmetic of the per-block path (set-up is FP64 in both).
+ *   CLAK_PREC_FP64  : rotation and grid sums on FP64 MFMA.
+ *   CLAK_PREC_MIXED : Z^T split into four int8 digit planes per eigenvector,
+ *                     rotation by int8 MFMA with exact int32 accumulation,
+ *                     rotated SNPs and the per-trait operand re-encoded as
+ *                     four int8 digit planes, grid sums by int8 MFMA with
+ *                     exact int32 accumulation (digit products of total
+ *                     weight 256^-4 and below dropped); FP64 Schur solve. */
+typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_precision;
+
+/* Plan flags (bitwise or). */
+#define CLAK_VAR_MODEL 0u   /* Var(b) = (X^T M^{-1} X)^{-1}                       */
+#define CLAK_VAR_PAPER 1u   /* Var(b) = s2_j (X^T M^{-1} X)^{-1}, as printed        */
+#define CLAK_OUT_SNP 0u     /* write the SNP effect b_ij[p-1] only                 */
+#define CLAK_OUT_FULL 2u    /* write all p components of b_ij                      */
+
+/* Genotype element types accepted by clak_run_block (values 0, 1, 2). */
+#define CLAK_G_U8 0
+#define CLAK_G_F16 1
+/* Output element types. */
+#define CLAK_OUT_F32 0
+#define CLAK_OUT_F64 1
+
+/* Per-cell flag values written by clak_run_block. */
+#define CLAK_CELL_OK 0
+#define CLAK_CELL_DEGENERATE 1  /* g_i in span(X_L) (or numerically so): b and SE are NaN */
+
+typedef struct clak_plan_s* clak_plan_t;
+
+/* Creates a plan for n individuals, p_L covariate columns (X_L, normally the
+ * intercept first), t traits and SNP blocks of at most max_block columns.
+ * Allocates host memory and a rocBLAS handle only; no device memory.
+ * Requires 1 <= p_L <= 16, n > p_L, t >= 1, max_block >= 1; MIXED requires
+ * n <= 32000 (int32 accumulation bound).  Errors: CLAK_E_ARG, CLAK_E_UNSUPPORTED,
+ * CLAK_E_DEVICE. */
+clak_status clak_plan_create(clak_plan_t* plan, int64_t n, int64_t p_L, int64_t t,
+                             int64_t max_block, int precision, uint32_t flags);
+
+/* Bytes of device workspace the plan needs (every buffer of the path: Z and
+ * its digit planes, rotated covariates and traits, per-trait operands and one
+ * SNP block's staging).  Always a multiple of 256. */
+clak_status clak_plan_workspace_size(clak_plan_t plan, size_t* bytes);
+
+/* Hands the plan a caller-owned device buffer of at least
+ * clak_plan_workspace_size bytes, 256-byte aligned.  It must stay allocated
+ * until the plan is destroyed or given another workspace (which resets the
+ * plan to the "no kinship" state).  Errors: CLAK_E_WORKSPACE. */
+clak_status clak_plan_set_workspace(clak_plan_t plan, void* d_ws, size_t bytes);
+
+/* HIP stream (hipStream_t, may be NULL for the default stream) on which every
+ * kernel of the plan is enqueued. */
+clak_status clak_plan_set_stream(clak_plan_t plan, void* hip_stream);
+
+/* Step 1 of the CLAK-Eig listing: Phi = Z W Z^T by the FP64 rocSOLVER divide
+ * and conquer eigensolver, then the int8 digit planes of Z^T (MIXED).
+ * d_Phi: n x n symmetric, leading dimension ld >= n; only its lower triangle
+ * is read; it is not modified.  Synchronous.  Errors: CLAK_E_ARG, CLAK_E_STATE,
+ * CLAK_E_EIG, CLAK_E_DEVICE. */
+clak_status clak_set_kinship(clak_plan_t plan, const double* d_Phi, int64_t ld);
+
+/* Alternative to clak_set_kinship: supplies Z (n x n orthonormal columns,
+ * leading dimension ldz) and w (n eigenvalues) of Phi directly.  Any
+ * orthonormal eigenbasis gives the same results.  Synchronous. */
+clak_status clak_set_eigen(clak_plan_t plan, const double* d_Z, int64_t ldz, const double* d_w);
+
+/* Step 2 of the listing (X_L := Z^T X_L) plus the per-SNP centring basis:
+ * X_L = Q_L R (FP64 Gram-Schmidt, twice), Z^T X_L and Z^T Q_L.  d_XL: n x p_L,
+ * leading dimension ld >= n.  Synchronous.  Errors: CLAK_E_ARG, CLAK_E_STATE,
+ * CLAK_E_COV_SINGULAR (rank-deficient X_L), CLAK_E_DEVICE. */
+clak_status clak_set_covariates(clak_plan_t plan, const double* d_XL, int64_t ld);
+
+/* Step 4 (Y := Z^T Y) and the per-trait part of the loop over traits:
+ * D_j = (s2_j (h2_j W + (1 - h2_j) I))^{-1}, S_TL,j = X_L^T D_j X_L (rotated
+ * X_L), b_T,j, its Cholesky factor, and the per-trait operand of the grid
+ * contraction.  d_Y: n x t, leading dimension ldy >= n; d_h2, d_s2: t values.
+ * Synchronous.  Errors: CLAK_E_ARG (h2 outside [0,1], s2 <= 0, non-finite
+ * values), CLAK_E_STATE, CLAK_E_NOT_SPD, CLAK_E_COV_SINGULAR, CLAK_E_DEVICE. */
+clak_status clak_set_traits(clak_plan_t plan, const double* d_Y, int64_t ldy,
+                            const double* d_h2, const double* d_s2);
+
+/* Step 3 of the listing on one block of SNPs (X_R := Z^T X_R) and the inner
+ * loop over (SNP, trait) cells of that block: W_R^T W_L, W_R^T W_R, W_R^T Y_j
+ * as contractions over n, then b_ij := S^{-1} b_ij.  Asynchronous.
+ *   d_G     : n x m_blk genotypes (column = one SNP), element type g_dtype,
+ *             leading dimension ldg >= n (in elements).
+ *   d_b     : SNP effects; with CLAK_OUT_SNP element (i, j) at d_b[i + j*ldo],
+ *             with CLAK_OUT_FULL component c at d_b[(i + j*ldo)*p + c].
+ *   d_se    : standard error of the SNP effect, element (i, j) at d_se[i + j*ldo].
+ *   out_dtype: CLAK_OUT_F32 or CLAK_OUT_F64 for d_b and d_se.
+ *   ldo     : >= m_blk.
+ *   d_flags : optional (NULL allowed) per-cell flags at d_flags[i + j*ldo].
+ * 1 <= m_blk <= max_block.  Errors: CLAK_E_ARG, CLAK_E_STATE, CLAK_E_DEVICE. */
+clak_status clak_run_block(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype,
+                           int64_t ldg, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                           uint8_t* d_flags);
+
+/* Destroys the plan (host memory, rocBLAS handle).  Never frees the workspace. */
+clak_status clak_plan_destroy(clak_plan_t plan);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* clak_last_error(void);
+
+/* Library version string. */
+const char* clak_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLAK_H */

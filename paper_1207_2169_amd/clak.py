@@ -1,0 +1,223 @@
+"""ctypes binding of libclak (``include/clak.h``): argument marshalling only.
+
+Every function carries the name of the C entry point it calls.  Matrices are
+passed as torch tensors on the GPU; a tensor standing for an n x c
+column-major matrix has logical shape (n, c) and unit stride along its first
+dimension (the transpose of a contiguous (c, ld) tensor), and its leading
+dimension is read from its strides.  Genotype blocks and outputs use the
+SNP-major layout of the C ABI directly: G is (m_blk, ldg) with one SNP per row,
+b and se are (t, ldo) with SNPs fastest.
+
+There is no fallback: if the library is not built or cannot be loaded, every
+call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libclak.so")
+
+CLAK_OK, CLAK_E_ARG, CLAK_E_STATE, CLAK_E_NOT_SPD, CLAK_E_COV_SINGULAR, CLAK_E_EIG, CLAK_E_WORKSPACE, \
+    CLAK_E_DEVICE, CLAK_E_UNSUPPORTED = range(9)
+STATUS_NAMES = {0: "CLAK_OK", 1: "CLAK_E_ARG", 2: "CLAK_E_STATE", 3: "CLAK_E_NOT_SPD",
+                4: "CLAK_E_COV_SINGULAR", 5: "CLAK_E_EIG", 6: "CLAK_E_WORKSPACE", 7: "CLAK_E_DEVICE",
+                8: "CLAK_E_UNSUPPORTED"}
+CLAK_PREC_FP64, CLAK_PREC_MIXED = 0, 1
+CLAK_VAR_MODEL, CLAK_VAR_PAPER = 0, 1
+CLAK_OUT_SNP, CLAK_OUT_FULL = 0, 2
+CLAK_G_U8, CLAK_G_F16 = 0, 1
+CLAK_OUT_F32, CLAK_OUT_F64 = 0, 1
+CLAK_CELL_OK, CLAK_CELL_DEGENERATE, CLAK_CELL_BAD_GENOTYPE = 0, 1, 2
+
+# exported symbol -> (restype, argtypes)
+_P, _I64, _I, _U32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+SIGNATURES = {
+    "clak_plan_create": (_I, [ctypes.POINTER(_P), _I64, _I64, _I64, _I64, _I, _U32]),
+    "clak_plan_workspace_size": (_I, [_P, ctypes.POINTER(_SZ)]),
+    "clak_plan_set_workspace": (_I, [_P, _P, _SZ]),
+    "clak_plan_set_stream": (_I, [_P, _P]),
+    "clak_set_kinship": (_I, [_P, _P, _I64]),
+    "clak_set_eigen": (_I, [_P, _P, _I64, _P]),
+    "clak_set_covariates": (_I, [_P, _P, _I64]),
+    "clak_set_traits": (_I, [_P, _P, _I64, _P, _P]),
+    "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
+    "clak_plan_destroy": (_I, [_P]),
+    "clak_last_error": (ctypes.c_char_p, []),
+    "clak_version": (ctypes.c_char_p, []),
+}
+
+_lib_handle = None
+
+
+class ClakError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def lib():
+    """The loaded libclak (raises if it is missing)."""
+    global _lib_handle
+    if _lib_handle is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"libclak.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib_handle = h
+    return _lib_handle
+
+
+def _check(status: int, where: str):
+    if status != CLAK_OK:
+        msg = lib().clak_last_error()
+        raise ClakError(status, where, msg.decode() if msg else "")
+
+
+def _dev(x: torch.Tensor, what: str, dtype=None):
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise ValueError(f"{what} must be a torch tensor on the GPU")
+    if dtype is not None and x.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {x.dtype}")
+    return x
+
+
+def _colmajor(A: torch.Tensor, what: str):
+    """(pointer, leading dimension, keep-alive tensor) of an n x c matrix."""
+    _dev(A, what, torch.float64)
+    if A.dim() == 1:
+        A = A.reshape(-1, 1)
+    if A.dim() != 2:
+        raise ValueError(f"{what} must be 2-D")
+    if A.stride(0) != 1 and A.shape[1] > 1:
+        A = A.t().contiguous().t()
+    ld = A.stride(1) if A.shape[1] > 1 else A.shape[0]
+    return A.data_ptr(), max(ld, A.shape[0]), A
+
+
+def clak_version() -> str:
+    return lib().clak_version().decode()
+
+
+def clak_plan_create(n: int, p_L: int, t: int, max_block: int, precision: int = CLAK_PREC_FP64,
+                     flags: int = 0) -> int:
+    h = _P()
+    _check(lib().clak_plan_create(ctypes.byref(h), n, p_L, t, max_block, precision, flags), "clak_plan_create")
+    return h.value
+
+
+def clak_plan_workspace_size(plan: int) -> int:
+    out = _SZ()
+    _check(lib().clak_plan_workspace_size(plan, ctypes.byref(out)), "clak_plan_workspace_size")
+    return out.value
+
+
+def clak_plan_set_workspace(plan: int, ws: torch.Tensor):
+    _dev(ws, "workspace", torch.uint8)
+    _check(lib().clak_plan_set_workspace(plan, ws.data_ptr(), ws.numel()), "clak_plan_set_workspace")
+
+
+def clak_plan_set_stream(plan: int, stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().clak_plan_set_stream(plan, s.cuda_stream), "clak_plan_set_stream")
+
+
+def clak_set_kinship(plan: int, Phi: torch.Tensor):
+    ptr, ld, _keep = _colmajor(Phi, "Phi")
+    _check(lib().clak_set_kinship(plan, ptr, ld), "clak_set_kinship")
+
+
+def clak_set_eigen(plan: int, Z: torch.Tensor, w: torch.Tensor):
+    ptr, ld, _keep = _colmajor(Z, "Z")
+    w = _dev(w, "w", torch.float64).contiguous()
+    _check(lib().clak_set_eigen(plan, ptr, ld, w.data_ptr()), "clak_set_eigen")
+
+
+def clak_set_covariates(plan: int, XL: torch.Tensor):
+    ptr, ld, _keep = _colmajor(XL, "X_L")
+    _check(lib().clak_set_covariates(plan, ptr, ld), "clak_set_covariates")
+
+
+def clak_set_traits(plan: int, Y: torch.Tensor, h2: torch.Tensor, s2: torch.Tensor):
+    ptr, ld, _keep = _colmajor(Y, "Y")
+    h2 = _dev(h2, "h2", torch.float64).contiguous()
+    s2 = _dev(s2, "s2", torch.float64).contiguous()
+    _check(lib().clak_set_traits(plan, ptr, ld, h2.data_ptr(), s2.data_ptr()), "clak_set_traits")
+
+
+def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
+                   flags: Optional[torch.Tensor] = None, m_blk: Optional[int] = None):
+    """G: (m_blk, ldg) uint8 or float16 SNP rows; b, se: (t, ldo[, p]) float32/64."""
+    _dev(G, "G")
+    if G.dtype == torch.uint8:
+        gdt = CLAK_G_U8
+    elif G.dtype == torch.float16:
+        gdt = CLAK_G_F16
+    else:
+        raise ValueError("G must be uint8 or float16")
+    if G.dim() != 2 or G.stride(1) != 1:
+        raise ValueError("G must be 2-D with contiguous rows (one SNP per row)")
+    m = G.shape[0] if m_blk is None else m_blk
+    _dev(b, "b")
+    _dev(se, "se")
+    if b.dtype != se.dtype or b.dtype not in (torch.float32, torch.float64):
+        raise ValueError("b and se must share dtype float32 or float64")
+    odt = CLAK_OUT_F32 if b.dtype == torch.float32 else CLAK_OUT_F64
+    if se.dim() != 2 or se.stride(1) != 1:
+        raise ValueError("se must be (t, ldo) with contiguous rows")
+    ldo = se.stride(0) if se.shape[0] > 1 else se.shape[1]
+    fptr = None
+    if flags is not None:
+        _dev(flags, "flags", torch.uint8)
+        if flags.shape != se.shape or flags.stride() != se.stride():
+            raise ValueError("flags must match the layout of se")
+        fptr = flags.data_ptr()
+    _check(lib().clak_run_block(plan, m, G.data_ptr(), gdt, G.stride(0), b.data_ptr(), se.data_ptr(), odt, ldo,
+                                fptr), "clak_run_block")
+
+
+def clak_plan_destroy(plan: int):
+    _check(lib().clak_plan_destroy(plan), "clak_plan_destroy")
+
+
+class Plan:
+    """Owns one plan and its torch-allocated workspace (convenience wrapper)."""
+
+    def __init__(self, n, p_L, t, max_block, precision=CLAK_PREC_FP64, flags=0, device=None,
+                 stream: Optional[torch.cuda.Stream] = None):
+        dev = torch.device("cuda" if device is None else device)
+        with torch.cuda.device(dev):
+            self.handle = clak_plan_create(n, p_L, t, max_block, precision, flags)
+            try:
+                nbytes = clak_plan_workspace_size(self.handle)
+                self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+                clak_plan_set_workspace(self.handle, self.workspace)
+                clak_plan_set_stream(self.handle, stream)
+            except Exception:
+                clak_plan_destroy(self.handle)
+                raise
+        self.n, self.p_L, self.t, self.max_block, self.precision, self.flags = n, p_L, t, max_block, precision, flags
+
+    def close(self):
+        if getattr(self, "handle", None):
+            clak_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

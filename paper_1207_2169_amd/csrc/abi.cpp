@@ -1,0 +1,326 @@
+// C ABI of libclak: argument validation, call-order state machine, workspace
+// carve-up, the FP64 eigensolver call and the per-block launch sequence.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "clak_internal.hpp"
+
+using namespace clak;
+
+namespace {
+
+thread_local std::string g_err;
+
+clak_status fail(clak_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+clak_status ok() {
+  g_err.clear();
+  return CLAK_OK;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(CLAK_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+Plan* as_plan(clak_plan_t h) { return reinterpret_cast<Plan*>(h); }
+
+clak_status need_state(const Plan* p, int min_state, const char* what) {
+  if (!p) return fail(CLAK_E_ARG, "%s: null plan", what);
+  if (p->state < min_state) {
+    static const char* names[] = {"workspace", "workspace", "kinship/eigen", "covariates", "traits"};
+    return fail(CLAK_E_STATE, "%s: call order: %s must be set first", what, names[min_state]);
+  }
+  return CLAK_OK;
+}
+
+bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
+
+clak_status sync_and_read_status(Plan* p) {
+  HIP_TRY(hipMemcpyAsync(p->hstat, p->ws.dstat, sizeof(int) * DS_COUNT, hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  return CLAK_OK;
+}
+
+}  // namespace
+
+namespace clak {
+
+// Carves the workspace.  With base == nullptr only the size is computed.
+size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return ptr;
+  };
+  const size_t np = p.n_pad, pl = p.pL, tp = p.t_pad, mb = p.mb_pad;
+  Workspace tmp;
+  Workspace& W = w ? *w : tmp;
+  W.Zt = (double*)take(8 * np * np);
+  W.w = (double*)take(8 * np);
+  W.evE = (double*)take(8 * np);
+  W.dstat = (int*)take(sizeof(int) * DS_COUNT);
+  W.QL = (double*)take(8 * np * pl);
+  W.Rm = (double*)take(8 * pl * pl);
+  W.Rinv = (double*)take(8 * pl * pl);
+  W.XLt = (double*)take(8 * np * pl);
+  W.Qt = (double*)take(8 * np * pl);
+  W.Yt = (double*)take(8 * np * p.t);
+  W.tpar = (double*)take(8 * tp * trait_stride(p.pL));
+  W.Gp = (int8_t*)take(mb * np);
+  W.sstat = (double*)take(8 * mb * snp_stride(p.pL));
+  if (p.prec == CLAK_PREC_FP64) {
+    W.X64 = (double*)take(8 * mb * np);
+    W.V64 = (double*)take(8 * tp * (pl + 1) * np);
+    W.D64 = (double*)take(8 * tp * np);
+  } else {
+    W.Zd = (int8_t*)take(4 * np * np);
+    W.zs = (double*)take(8 * np);
+    W.Xd = (int8_t*)take(8 * mb * np);
+    W.Vd = (int8_t*)take(4 * tp * (pl + 1) * np);
+    W.Dd = (int8_t*)take(4 * tp * np);
+    W.vs = (double*)take(8 * tp * (pl + 1));
+    W.ds = (double*)take(8 * tp);
+  }
+  return off;
+}
+
+}  // namespace clak
+
+extern "C" {
+
+const char* clak_last_error(void) { return g_err.c_str(); }
+
+const char* clak_version(void) { return "clak-mi355x 0.1 (gfx950)"; }
+
+clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t, int64_t max_block,
+                             int precision, uint32_t flags) {
+  if (!out) return fail(CLAK_E_ARG, "plan_create: null output pointer");
+  *out = nullptr;
+  if (p_L < 1 || p_L > MAX_PL) return fail(CLAK_E_ARG, "plan_create: p_L=%lld outside [1,%d]", (long long)p_L, MAX_PL);
+  if (n <= p_L) return fail(CLAK_E_ARG, "plan_create: need n > p_L (n=%lld)", (long long)n);
+  if (t < 1) return fail(CLAK_E_ARG, "plan_create: t must be >= 1");
+  if (max_block < 1) return fail(CLAK_E_ARG, "plan_create: max_block must be >= 1");
+  if (precision != CLAK_PREC_FP64 && precision != CLAK_PREC_MIXED)
+    return fail(CLAK_E_ARG, "plan_create: unknown precision %d", precision);
+  if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL)) return fail(CLAK_E_ARG, "plan_create: unknown flags 0x%x", flags);
+  if (precision == CLAK_PREC_MIXED && n > MIXED_MAX_N)
+    return fail(CLAK_E_UNSUPPORTED, "plan_create: mixed precision supports n <= %lld", (long long)MIXED_MAX_N);
+  if (n > (int64_t)1 << 20 || t > (int64_t)1 << 24 || max_block > (int64_t)1 << 26)
+    return fail(CLAK_E_UNSUPPORTED, "plan_create: size too large");
+  Plan* p = new (std::nothrow) Plan();
+  if (!p) return fail(CLAK_E_DEVICE, "plan_create: out of host memory");
+  p->n = n;
+  p->pL = p_L;
+  p->t = t;
+  p->max_block = max_block;
+  p->prec = precision;
+  p->flags = flags;
+  p->n_pad = roundup(n, KPAD);
+  p->mb_pad = roundup(max_block, SNP_PAD);
+  p->t_pad = roundup(t, TRAIT_PAD);
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    delete p;
+    return fail(CLAK_E_DEVICE, "plan_create: no HIP device");
+  }
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success) {
+    delete p;
+    return fail(CLAK_E_DEVICE, "plan_create: rocblas_create_handle failed");
+  }
+  p->rocblas = h;
+  if (hipHostMalloc((void**)&p->hstat, sizeof(int) * DS_COUNT, hipHostMallocDefault) != hipSuccess) {
+    rocblas_destroy_handle(h);
+    delete p;
+    return fail(CLAK_E_DEVICE, "plan_create: pinned status buffer");
+  }
+  *out = reinterpret_cast<clak_plan_t>(p);
+  return ok();
+}
+
+clak_status clak_plan_workspace_size(clak_plan_t h, size_t* bytes) {
+  Plan* p = as_plan(h);
+  if (!p || !bytes) return fail(CLAK_E_ARG, "plan_workspace_size: null argument");
+  *bytes = workspace_bytes(*p, nullptr, nullptr);
+  return ok();
+}
+
+clak_status clak_plan_set_workspace(clak_plan_t h, void* d_ws, size_t bytes) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_set_workspace: null plan");
+  if (!d_ws) return fail(CLAK_E_WORKSPACE, "plan_set_workspace: null workspace");
+  if (!aligned(d_ws, 256)) return fail(CLAK_E_WORKSPACE, "plan_set_workspace: workspace not 256-byte aligned");
+  size_t need = workspace_bytes(*p, nullptr, nullptr);
+  if (bytes < need)
+    return fail(CLAK_E_WORKSPACE, "plan_set_workspace: %zu bytes given, %zu needed", bytes, need);
+  p->ws_base = d_ws;
+  p->ws_bytes = bytes;
+  workspace_bytes(*p, &p->ws, (char*)d_ws);
+  p->state = ST_WS;
+  return ok();
+}
+
+clak_status clak_plan_set_stream(clak_plan_t h, void* stream) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_set_stream: null plan");
+  p->stream = (hipStream_t)stream;
+  return ok();
+}
+
+static clak_status finish_eigen(Plan* p) {
+  // zero the status words, validate the eigenpairs, split Z^T into digits
+  HIP_TRY(launch_check_eigen(*p));
+  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p));
+  clak_status s = sync_and_read_status(p);
+  if (s != CLAK_OK) return s;
+  if (p->hstat[DS_EIGVAL]) return fail(CLAK_E_ARG, "non-finite eigenvalues or eigenvectors");
+  p->state = ST_EIG;
+  return ok();
+}
+
+clak_status clak_set_kinship(clak_plan_t h, const double* d_Phi, int64_t ld) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_WS, "set_kinship");
+  if (s) return s;
+  if (!d_Phi) return fail(CLAK_E_ARG, "set_kinship: null Phi");
+  if (ld < p->n) return fail(CLAK_E_ARG, "set_kinship: ld=%lld < n", (long long)ld);
+  p->state = ST_WS;
+  const int64_t n = p->n, np = p->n_pad;
+  Workspace& W = p->ws;
+  HIP_TRY(hipMemsetAsync(W.Zt, 0, sizeof(double) * np * np, p->stream));
+  HIP_TRY(hipMemsetAsync(W.w, 0, sizeof(double) * np, p->stream));
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(hipMemcpy2DAsync(W.Zt, sizeof(double) * np, d_Phi, sizeof(double) * ld, sizeof(double) * n, n,
+                           hipMemcpyDeviceToDevice, p->stream));
+  rocblas_handle rb = (rocblas_handle)p->rocblas;
+  if (rocblas_set_stream(rb, p->stream) != rocblas_status_success)
+    return fail(CLAK_E_DEVICE, "set_kinship: rocblas_set_stream failed");
+  rocblas_status rs = rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_lower, (rocblas_int)n, W.Zt,
+                                       (rocblas_int)np, W.w, W.evE, W.dstat + DS_EIG_INFO);
+  if (rs != rocblas_status_success) return fail(CLAK_E_DEVICE, "set_kinship: rocsolver_dsyevd status %d", (int)rs);
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_EIG_INFO] != 0)
+    return fail(CLAK_E_EIG, "set_kinship: eigensolver did not converge (info=%d)", p->hstat[DS_EIG_INFO]);
+  return finish_eigen(p);
+}
+
+clak_status clak_set_eigen(clak_plan_t h, const double* d_Z, int64_t ldz, const double* d_w) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_WS, "set_eigen");
+  if (s) return s;
+  if (!d_Z || !d_w) return fail(CLAK_E_ARG, "set_eigen: null Z or w");
+  if (ldz < p->n) return fail(CLAK_E_ARG, "set_eigen: ldz=%lld < n", (long long)ldz);
+  p->state = ST_WS;
+  const int64_t n = p->n, np = p->n_pad;
+  Workspace& W = p->ws;
+  HIP_TRY(hipMemsetAsync(W.Zt, 0, sizeof(double) * np * np, p->stream));
+  HIP_TRY(hipMemsetAsync(W.w, 0, sizeof(double) * np, p->stream));
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(hipMemcpy2DAsync(W.Zt, sizeof(double) * np, d_Z, sizeof(double) * ldz, sizeof(double) * n, n,
+                           hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemcpyAsync(W.w, d_w, sizeof(double) * n, hipMemcpyDeviceToDevice, p->stream));
+  return finish_eigen(p);
+}
+
+clak_status clak_set_covariates(clak_plan_t h, const double* d_XL, int64_t ld) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_EIG, "set_covariates");
+  if (s) return s;
+  if (!d_XL) return fail(CLAK_E_ARG, "set_covariates: null X_L");
+  if (ld < p->n) return fail(CLAK_E_ARG, "set_covariates: ld=%lld < n", (long long)ld);
+  p->state = ST_EIG;
+  Workspace& W = p->ws;
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(launch_covariates(*p, d_XL, ld));
+  HIP_TRY(launch_rotate_real(*p, d_XL, ld, p->pL, W.XLt, p->n_pad));
+  HIP_TRY(launch_rotate_real(*p, W.QL, p->n_pad, p->pL, W.Qt, p->n_pad));
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_COV] == 1) return fail(CLAK_E_ARG, "set_covariates: non-finite X_L");
+  if (p->hstat[DS_COV] == 2) return fail(CLAK_E_COV_SINGULAR, "set_covariates: X_L is rank deficient");
+  p->state = ST_COV;
+  return ok();
+}
+
+clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const double* d_h2,
+                            const double* d_s2) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_COV, "set_traits");
+  if (s) return s;
+  if (!d_Y || !d_h2 || !d_s2) return fail(CLAK_E_ARG, "set_traits: null Y, h2 or s2");
+  if (ldy < p->n) return fail(CLAK_E_ARG, "set_traits: ldy=%lld < n", (long long)ldy);
+  p->state = ST_COV;
+  Workspace& W = p->ws;
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(launch_rotate_real(*p, d_Y, ldy, p->t, W.Yt, p->n_pad));
+  // per-trait h2 and s2 travel through the parameter block (slot pL*pL+pL: s2, +1: h2)
+  const int64_t ts = trait_stride(p->pL);
+  HIP_TRY(hipMemcpy2DAsync(W.tpar + p->pL * p->pL + p->pL, sizeof(double) * ts, d_s2, sizeof(double),
+                           sizeof(double), p->t, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(hipMemcpy2DAsync(W.tpar + p->pL * p->pL + p->pL + 1, sizeof(double) * ts, d_h2, sizeof(double),
+                           sizeof(double), p->t, hipMemcpyDeviceToDevice, p->stream));
+  HIP_TRY(launch_traits(*p));
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_TRAIT_ARG])
+    return fail(CLAK_E_ARG, "set_traits: %d trait(s) with h2 outside [0,1], s2 <= 0 or non-finite values",
+                p->hstat[DS_TRAIT_ARG]);
+  if (p->hstat[DS_TRAIT_SPD])
+    return fail(CLAK_E_NOT_SPD, "set_traits: M_j not positive definite for %d trait(s)", p->hstat[DS_TRAIT_SPD]);
+  if (p->hstat[DS_TRAIT_COV])
+    return fail(CLAK_E_COV_SINGULAR, "set_traits: X_L^T M_j^-1 X_L singular for %d trait(s)",
+                p->hstat[DS_TRAIT_COV]);
+  p->state = ST_READY;
+  return ok();
+}
+
+clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
+                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_READY, "run_block");
+  if (s) return s;
+  if (m_blk < 1 || m_blk > p->max_block)
+    return fail(CLAK_E_ARG, "run_block: m_blk=%lld outside [1, max_block=%lld]", (long long)m_blk,
+                (long long)p->max_block);
+  if (!d_G || !d_b || !d_se) return fail(CLAK_E_ARG, "run_block: null G, b or se");
+  if (g_dtype != CLAK_G_U8 && g_dtype != CLAK_G_F16) return fail(CLAK_E_ARG, "run_block: unknown g_dtype %d", g_dtype);
+  if (out_dtype != CLAK_OUT_F32 && out_dtype != CLAK_OUT_F64)
+    return fail(CLAK_E_ARG, "run_block: unknown out_dtype %d", out_dtype);
+  if (ldg < p->n) return fail(CLAK_E_ARG, "run_block: ldg=%lld < n", (long long)ldg);
+  if (ldo < m_blk) return fail(CLAK_E_ARG, "run_block: ldo=%lld < m_blk", (long long)ldo);
+  const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
+  if (!aligned(d_b, esz) || !aligned(d_se, esz)) return fail(CLAK_E_ARG, "run_block: misaligned output");
+  if (g_dtype == CLAK_G_F16 && !aligned(d_G, 2)) return fail(CLAK_E_ARG, "run_block: misaligned F16 genotypes");
+  HIP_TRY(launch_ingest(*p, m_blk, d_G, g_dtype, ldg));
+  HIP_TRY(launch_rotate_snps(*p, m_blk));
+  HIP_TRY(launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags));
+  return ok();
+}
+
+clak_status clak_plan_destroy(clak_plan_t h) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_destroy: null plan");
+  if (p->rocblas) rocblas_destroy_handle((rocblas_handle)p->rocblas);
+  if (p->hstat) (void)hipHostFree(p->hstat);
+  delete p;
+  return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Internal declarations of libclak: plan state, workspace carve-up and the
+// kernel launchers shared by the ABI layer and the HIP translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/clak.h"
+
+namespace clak {
+
+// Padding of the individual / eigen-index axis (the contraction axis K of
+// every GEMM on the path) and of the SNP axis of a block.
+constexpr int64_t KPAD = 128;
+constexpr int64_t SNP_PAD = 128;
+constexpr int64_t TRAIT_PAD = 16;
+constexpr int MAX_PL = 16;
+// int8 digit encoding: a value v with |v| <= s is stored as
+// q = rint(v / s * QMAX), |q| <= QMAX < 2^31, split into four base-256 digits.
+constexpr double QMAX = 2130706432.0;  // 127 * 2^24
+constexpr int64_t MIXED_MAX_N = 32000; // int32 accumulators of the grid sums stay exact below this
+
+__host__ __device__ inline int64_t roundup(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Per-SNP statistics written by the ingest kernel (doubles, stride snp_stride):
+//   [0, pL)      v = Q_L^T g            (centring coefficients in the Q_L basis)
+//   [pL, 2pL)    gamma = R^{-1} v       (centring coefficients in the X_L basis)
+//   2pL          ||g - Q_L v||          (digit scale of the rotated SNP)
+//   2pL + 1      cell flag of the SNP (0 ok, 1 degenerate, 2 bad genotype)
+__host__ __device__ inline int64_t snp_stride(int64_t pL) { return 2 * pL + 2; }
+// Per-trait parameters written by the trait kernel (doubles, stride trait_stride):
+//   [0, pL*pL)   L^{-1} (row-major, lower), L L^T = S_TL
+//   [pL*pL, pL*pL+pL)  u = S_TL^{-1} b_T
+//   pL*pL+pL     s2
+__host__ __device__ inline int64_t trait_stride(int64_t pL) { return pL * pL + pL + 2; }
+
+enum DevStatus : int {
+  DS_EIG_INFO = 0,     // rocSOLVER info
+  DS_COV = 1,          // 0 ok, 1 non-finite X_L, 2 rank deficient
+  DS_TRAIT_ARG = 2,    // count of traits with bad h2 / s2 / non-finite y
+  DS_TRAIT_SPD = 3,    // count of traits with h2 w_k + 1 - h2 <= 0
+  DS_TRAIT_COV = 4,    // count of traits whose S_TL is not positive definite
+  DS_EIGVAL = 5,       // non-finite eigenvalue / eigenvector input
+  DS_COUNT = 64
+};
+
+struct Workspace {
+  // common
+  double* Zt = nullptr;     // n_pad x n_pad: row k (stride n_pad) = eigenvector k, zero padded
+  double* w = nullptr;      // n_pad eigenvalues (zero beyond n)
+  double* evE = nullptr;    // n_pad, eigensolver scratch
+  int* dstat = nullptr;     // DS_COUNT device status words
+  double* QL = nullptr;     // n_pad x pL, column-major: orthonormal basis of X_L, zero padded
+  double* Rm = nullptr;     // pL x pL row-major upper triangle R, X_L = Q_L R
+  double* Rinv = nullptr;   // pL x pL row-major R^{-1}
+  double* XLt = nullptr;    // n_pad x pL column-major: Z^T X_L
+  double* Qt = nullptr;     // n_pad x pL column-major: Z^T Q_L
+  double* Yt = nullptr;     // n_pad x t  column-major: Z^T Y
+  double* tpar = nullptr;   // t_pad x trait_stride
+  // per block
+  int8_t* Gp = nullptr;     // mb_pad x n_pad: SNP rows, individuals contiguous, zero padded
+  double* sstat = nullptr;  // mb_pad x snp_stride
+  // FP64 path
+  double* X64 = nullptr;    // mb_pad x n_pad: rotated, centred SNPs (row = SNP)
+  double* V64 = nullptr;    // t_pad*(pL+1) x n_pad: per-trait operand columns (row = column)
+  double* D64 = nullptr;    // t_pad x n_pad: d_j
+  // mixed path
+  int8_t* Zd = nullptr;     // 4 planes x n_pad x n_pad: digits of Z^T rows
+  double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
+  int8_t* Xd = nullptr;     // 8 planes x mb_pad x n_pad: digits of x and x^2 (row = SNP)
+  int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) x n_pad
+  int8_t* Dd = nullptr;     // 4 planes x t_pad x n_pad
+  double* vs = nullptr;     // t_pad*(pL+1) digit scales of the operand columns
+  double* ds = nullptr;     // t_pad digit scales of d_j
+};
+
+enum PlanState { ST_CREATED = 0, ST_WS = 1, ST_EIG = 2, ST_COV = 3, ST_READY = 4 };
+
+struct Plan {
+  int64_t n = 0, pL = 0, t = 0, max_block = 0;
+  int prec = CLAK_PREC_FP64;
+  uint32_t flags = 0;
+  int64_t n_pad = 0, mb_pad = 0, t_pad = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void* rocblas = nullptr;  // rocblas_handle
+  void* ws_base = nullptr;
+  size_t ws_bytes = 0;
+  Workspace ws;
+  int state = ST_CREATED;
+  int* hstat = nullptr;     // pinned host mirror of dstat
+};
+
+size_t workspace_bytes(const Plan& p, Workspace* carve, char* base);
+
+// ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
+// set-up
+hipError_t launch_split_digits(const Plan& p);
+hipError_t launch_covariates(const Plan& p, const double* d_XL, int64_t ld);
+hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64_t ncols, double* out,
+                              int64_t ldo);
+hipError_t launch_traits(const Plan& p);
+hipError_t launch_check_eigen(const Plan& p);
+// per block
+hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);
+hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);
+hipError_t launch_grid(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                       uint8_t* d_flags);
+
+}  // namespace clak

@@ -1,0 +1,142 @@
+"""Status codes and the call-order state machine of the C ABI, forced from
+the host (every kernel still runs to completion)."""
+import numpy as np
+import pytest
+
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _col(a):
+    return _t(np.ascontiguousarray(np.asarray(a).T)).t()
+
+
+@pytest.fixture(scope="module")
+def w():
+    return make_workload(0, n=96, m=20, kin_cols=200)
+
+
+def test_status_codes(w):
+    import torch
+
+    from paper_1207_2169_amd import clak
+    from paper_1207_2169_amd.clak import ClakError
+    print("ABI status codes", flush=True)
+    with pytest.raises(ClakError) as e:
+        clak.clak_plan_create(10, 0, 1, 10)
+    assert e.value.status == clak.CLAK_E_ARG
+    with pytest.raises(ClakError) as e:
+        clak.clak_plan_create(40000, 3, 1, 10, clak.CLAK_PREC_MIXED)
+    assert e.value.status == clak.CLAK_E_UNSUPPORTED
+    h = clak.clak_plan_create(w.n, w.pL, 2, 16)
+    try:
+        # no workspace yet
+        with pytest.raises(ClakError) as e:
+            clak.clak_set_kinship(h, _t(w.Phi))
+        assert e.value.status == clak.CLAK_E_STATE
+        nbytes = clak.clak_plan_workspace_size(h)
+        assert nbytes % 256 == 0
+        small = torch.empty(nbytes - 256, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ClakError) as e:
+            clak.clak_plan_set_workspace(h, small)
+        assert e.value.status == clak.CLAK_E_WORKSPACE
+        ws = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+        with pytest.raises(ClakError) as e:
+            clak.clak_plan_set_workspace(h, ws[1:])
+        assert e.value.status == clak.CLAK_E_WORKSPACE
+        clak.clak_plan_set_workspace(h, ws)
+        clak.clak_plan_set_stream(h)
+        # covariates before kinship
+        with pytest.raises(ClakError) as e:
+            clak.clak_set_covariates(h, _col(w.XL))
+        assert e.value.status == clak.CLAK_E_STATE
+        clak.clak_set_kinship(h, _t(w.Phi))
+        # rank-deficient covariates
+        XLbad = np.c_[w.XL[:, :2], w.XL[:, 1] * 2.0]
+        with pytest.raises(ClakError) as e:
+            clak.clak_set_covariates(h, _col(XLbad))
+        assert e.value.status == clak.CLAK_E_COV_SINGULAR
+        XLnan = w.XL.copy()
+        XLnan[3, 2] = np.nan
+        with pytest.raises(ClakError) as e:
+            clak.clak_set_covariates(h, _col(XLnan))
+        assert e.value.status == clak.CLAK_E_ARG
+        clak.clak_set_covariates(h, _col(w.XL))
+        G = _t(w.genotypes(0, 16))
+        b = torch.empty((2, 16), dtype=torch.float64, device="cuda")
+        se = torch.empty_like(b)
+        with pytest.raises(ClakError) as e:
+            clak.clak_run_block(h, G, b, se)
+        assert e.value.status == clak.CLAK_E_STATE
+        Y = _col(np.c_[w.Y, w.Y])
+        for h2, s2 in [([0.5, 1.2], [1.0, 1.0]), ([0.5, -0.1], [1.0, 1.0]), ([0.5, 0.5], [1.0, 0.0]),
+                       ([0.5, np.nan], [1.0, 1.0])]:
+            with pytest.raises(ClakError) as e:
+                clak.clak_set_traits(h, Y, _t(np.array(h2)), _t(np.array(s2)))
+            assert e.value.status == clak.CLAK_E_ARG
+        clak.clak_set_traits(h, Y, _t(np.array([0.5, 1.0])), _t(np.array([1.0, 2.0])))
+        # block larger than max_block, bad leading dimension
+        with pytest.raises(ClakError) as e:
+            clak.clak_run_block(h, _t(w.genotypes(0, 17)), torch.empty((2, 17), dtype=torch.float64,
+                                device="cuda"), torch.empty((2, 17), dtype=torch.float64, device="cuda"))
+        assert e.value.status == clak.CLAK_E_ARG
+        clak.clak_run_block(h, G, b, se)
+        torch.cuda.synchronize()
+        assert torch.isfinite(b).all() and (se > 0).all()
+        # indefinite kinship with h2 = 1: not positive definite
+        ev, V = np.linalg.eigh(w.Phi)
+        ev[0] = -0.2
+        clak.clak_set_kinship(h, _t((V * ev) @ V.T))
+        clak.clak_set_covariates(h, _col(w.XL))
+        with pytest.raises(ClakError) as e:
+            clak.clak_set_traits(h, Y, _t(np.array([0.5, 1.0])), _t(np.array([1.0, 1.0])))
+        assert e.value.status == clak.CLAK_E_NOT_SPD
+        # traits invalidated: run_block refuses
+        with pytest.raises(ClakError) as e:
+            clak.clak_run_block(h, G, b, se)
+        assert e.value.status == clak.CLAK_E_STATE
+    finally:
+        clak.clak_plan_destroy(h)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_and_bad_genotypes(w, prec):
+    """Monomorphic, all-zero and covariate-equal SNPs give NaN and flag 1;
+    a genotype outside {0, 1, 2} gives NaN and flag 2; the rest match the
+    oracle."""
+    import torch
+
+    import oracle
+    from paper_1207_2169_amd import clak
+    print(f"degenerate SNPs precision={prec}", flush=True)
+    n = w.n
+    XL = w.XL.copy()
+    g = w.genotypes(0, 8).astype(np.uint8)
+    g[0] = 2
+    g[1] = 0
+    g[2] = XL[:, 1].astype(np.uint8)
+    g[3, 5] = 3
+    with clak.Plan(n, w.pL, 1, 8, prec) as plan:
+        clak.clak_set_kinship(plan.handle, _t(w.Phi))
+        clak.clak_set_covariates(plan.handle, _col(XL))
+        clak.clak_set_traits(plan.handle, _col(w.Y), _t(w.h2), _t(w.s2))
+        b = torch.empty((1, 8), dtype=torch.float64, device="cuda")
+        se = torch.empty_like(b)
+        fl = torch.empty((1, 8), dtype=torch.uint8, device="cuda")
+        clak.clak_run_block(plan.handle, _t(g), b, se, fl)
+        torch.cuda.synchronize()
+        b, se, fl = b.cpu().numpy()[0], se.cpu().numpy()[0], fl.cpu().numpy()[0]
+    assert list(fl[:4]) == [1, 1, 1, 2] and (fl[4:] == 0).all()
+    assert np.isnan(b[:4]).all() and np.isnan(se[:4]).all()
+    rb, rv, rf = oracle.gls_cells(w.Phi, XL, g[4:].T.astype(float), w.Y, w.h2, w.s2, np.arange(4),
+                                  np.zeros(4, int))
+    tol = 1e-9 if prec == 0 else 1e-6
+    rse = np.sqrt(rv[:, -1, -1])
+    assert np.max(np.abs(b[4:] - rb[:, -1]) / rse) < tol
+    assert np.max(np.abs(se[4:] - rse) / rse) < tol
