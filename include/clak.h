@@ -96,7 +96,7 @@ typedef struct clak_plan_s* clak_plan_t;
  * intercept first), t traits and SNP blocks of at most max_block columns.
  * Allocates host memory and a rocBLAS handle only; no device memory.
  * Requires 1 <= p_L <= 16, n > p_L, t >= 1, max_block >= 1; MIXED requires
- * n <= 32000 (int32 accumulation bound).  Errors: CLAK_E_ARG, CLAK_E_UNSUPPORTED,
+ * p_L <= 8 and n <= 32000 (int32 accumulation bound).  Errors: CLAK_E_ARG, CLAK_E_UNSUPPORTED,
  * CLAK_E_DEVICE. */
 clak_status clak_plan_create(clak_plan_t* plan, int64_t n, int64_t p_L, int64_t t,
                              int64_t max_block, int precision, uint32_t flags);

@@ -85,13 +85,20 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   W.tpar = (double*)take(8 * tp * trait_stride(p.pL));
   W.Gp = (int8_t*)take(mb * np);
   W.sstat = (double*)take(8 * mb * snp_stride(p.pL));
-  if (p.prec == CLAK_PREC_FP64) {
-    W.X64 = (double*)take(8 * mb * np);
+  if (p.prec == CLAK_PREC_FP64 || p.fused_t1) {
     W.V64 = (double*)take(8 * tp * (pl + 1) * np);
     W.D64 = (double*)take(8 * tp * np);
+  }
+  if (p.prec == CLAK_PREC_FP64) {
+    W.X64 = (double*)take(8 * mb * np);
+  } else if (p.fused_t1) {
+    W.Zd = (int8_t*)take(4 * np * np);
+    W.zs = (double*)take(8 * np);
+    W.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
   } else {
     W.Zd = (int8_t*)take(4 * np * np);
     W.zs = (double*)take(8 * np);
+    W.X64 = (double*)take(8 * mb * np);
     W.Xd = (int8_t*)take(8 * mb * np);
     W.Vd = (int8_t*)take(4 * tp * (pl + 1) * np);
     W.Dd = (int8_t*)take(4 * tp * np);
@@ -120,6 +127,8 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   if (precision != CLAK_PREC_FP64 && precision != CLAK_PREC_MIXED)
     return fail(CLAK_E_ARG, "plan_create: unknown precision %d", precision);
   if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL)) return fail(CLAK_E_ARG, "plan_create: unknown flags 0x%x", flags);
+  if (precision == CLAK_PREC_MIXED && p_L > 8)
+    return fail(CLAK_E_UNSUPPORTED, "plan_create: mixed precision supports p_L <= 8");
   if (precision == CLAK_PREC_MIXED && n > MIXED_MAX_N)
     return fail(CLAK_E_UNSUPPORTED, "plan_create: mixed precision supports n <= %lld", (long long)MIXED_MAX_N);
   if (n > (int64_t)1 << 20 || t > (int64_t)1 << 24 || max_block > (int64_t)1 << 26)
@@ -135,6 +144,7 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   p->n_pad = roundup(n, KPAD);
   p->mb_pad = roundup(max_block, SNP_PAD);
   p->t_pad = roundup(t, TRAIT_PAD);
+  p->fused_t1 = (precision == CLAK_PREC_MIXED && t == 1);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(CLAK_E_DEVICE, "plan_create: no HIP device");

@@ -30,7 +30,9 @@ __host__ __device__ inline int64_t roundup(int64_t x, int64_t m) { return (x + m
 //   [pL, 2pL)    gamma = R^{-1} v       (centring coefficients in the X_L basis)
 //   2pL          ||g - Q_L v||          (digit scale of the rotated SNP)
 //   2pL + 1      cell flag of the SNP (0 ok, 1 degenerate, 2 bad genotype)
-__host__ __device__ inline int64_t snp_stride(int64_t pL) { return 2 * pL + 2; }
+//   2pL + 2      max_k |x~_k| of the rotated, centred SNP (mixed path; written
+//                by an atomic max on its bit pattern, so it is order-independent)
+__host__ __device__ inline int64_t snp_stride(int64_t pL) { return 2 * pL + 3; }
 // Per-trait parameters written by the trait kernel (doubles, stride trait_stride):
 //   [0, pL*pL)   L^{-1} (row-major, lower), L L^T = S_TL
 //   [pL*pL, pL*pL+pL)  u = S_TL^{-1} b_T
@@ -63,10 +65,12 @@ struct Workspace {
   // per block
   int8_t* Gp = nullptr;     // mb_pad x n_pad: SNP rows, individuals contiguous, zero padded
   double* sstat = nullptr;  // mb_pad x snp_stride
-  // FP64 path
-  double* X64 = nullptr;    // mb_pad x n_pad: rotated, centred SNPs (row = SNP)
+  // rotated, centred SNPs in FP64 (both paths)
+  double* X64 = nullptr;    // mb_pad x n_pad: row = SNP, eigen index contiguous
+  // FP64 per-trait operand (FP64 path; mixed path when the fused t = 1 kernel runs)
   double* V64 = nullptr;    // t_pad*(pL+1) x n_pad: per-trait operand columns (row = column)
   double* D64 = nullptr;    // t_pad x n_pad: d_j
+  double* part = nullptr;   // fused t = 1 kernel: (n_pad/64) x mb_pad x (pL+2) partial sums
   // mixed path
   int8_t* Zd = nullptr;     // 4 planes x n_pad x n_pad: digits of Z^T rows
   double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
@@ -91,6 +95,7 @@ struct Plan {
   size_t ws_bytes = 0;
   Workspace ws;
   int state = ST_CREATED;
+  bool fused_t1 = false;    // mixed path with a single trait: rotate-and-reduce kernel
   int* hstat = nullptr;     // pinned host mirror of dstat
 };
 

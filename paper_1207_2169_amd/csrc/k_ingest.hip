@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(256) k_ingest(int64_t n, int64_t np, int pL, i
       }
       st[2 * pL] = flag ? 1.0 : sqrt(res);
       st[2 * pL + 1] = (double)flag;
+      st[2 * pL + 2] = 0.0;
     }
   }
 }

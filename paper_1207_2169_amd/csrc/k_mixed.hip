@@ -1,13 +1,394 @@
-// int8 digit-plane MFMA kernels of the mixed-precision path (placeholder).
+// int8 digit-plane MFMA kernels of the mixed-precision path.
+//
+// Every real operand is carried as four int8 digit planes with one FP64 scale
+// (per eigenvector row of Z^T, per SNP, per operand column): a value v with
+// |v| <= s is q = rint(v / s * QMAX) = d0 256^3 + d1 256^2 + d2 256 + d3.
+// Genotypes 0/1/2 are exact int8.  v_mfma_i32_16x16x64_i8 accumulates digit
+// products exactly in int32, so the only rounding of the contractions is the
+// encoding of their operands (and, in the grid, the digit products of weight
+// 256^-4 and below, which are dropped).
 #include "common.cuh"
+#include "schur.cuh"
 
 namespace clak {
 
-hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) { return hipErrorNotSupported; }
+// v_mfma_i32_16x16x64_i8 lane layout (gfx950): lane l supplies 16 bytes of
+// row l%16 of A and of column l%16 of B, both covering the same 16 values of
+// the 64-deep contraction (chunk l/16); result register r holds C[4(l/16)+r][l%16].
+__device__ __forceinline__ v4i mfma_i8(v4i a, v4i b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
+}
+
+constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-conflict-free 16-byte reads)
+
+// ------------------------------------------------------------------ rotation
+//
+// Step 3 of the multi-trait CLAK-Eig listing on one SNP block, X~ = Z^T G:
+// a 64 (eigen rows) x 128 (SNPs) tile per work-group, four waves of 32 x 64,
+// four digit planes of Z^T against the same genotype fragment.  Per element,
+// the planes are recombined exactly in FP64, scaled, and the centring term
+// (Z^T Q_L)[k] . v(i) is subtracted.  Then
+//   EPI 0: the FP64 value is stored (SNP-major) and the SNP's max |x~_k| is
+//          raised by an atomic max, for the digit encoding of the grid operand;
+//   EPI 1: (single trait) the cell sums c', r', a of this tile's 64 rows are
+//          formed in FP64 against the FP64 trait operand and written as one
+//          partial per (row tile, SNP); x~ never leaves the chip.
+template <int PL, int EPI>
+__global__ void __launch_bounds__(256) k_rot_i8(int64_t np, int64_t mb, int64_t mbp, const int8_t* __restrict__ Zd,
+                                                const double* __restrict__ zs, const int8_t* __restrict__ Gp,
+                                                const double* __restrict__ Qt, double* __restrict__ sstat,
+                                                double* __restrict__ X, const double* __restrict__ V,
+                                                const double* __restrict__ Dv, double* __restrict__ part) {
+  constexpr int BM = 64, BN = 128, BK = 64, NP = PL + 2;
+  __shared__ __attribute__((aligned(16))) int8_t As[4][BM][LROW];
+  __shared__ __attribute__((aligned(16))) int8_t Bs[BN][LROW];
+  __shared__ double Ps[EPI == 1 ? 2 * BN * NP : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int wr = wid >> 1, wc = wid & 1;
+  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t zplane = np * np;
+
+  v4i acc[2][4][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) acc[i][j][p] = (v4i){0, 0, 0, 0};
+
+  // global -> register staging of the next K slice, then register -> LDS
+  v4i ra[4], rb[2];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // plane q, row tid/4, 16-byte chunk tid%4
+      ra[q] = *(const v4i*)(Zd + q * zplane + (m0 + (tid >> 2)) * np + k0 + 16 * (tid & 3));
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = tid + 256 * q;
+      rb[q] = *(const v4i*)(Gp + (n0 + (c >> 2)) * np + k0 + 16 * (c & 3));
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) *(v4i*)(&As[q][tid >> 2][16 * (tid & 3)]) = ra[q];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int c = tid + 256 * q;
+      *(v4i*)(&Bs[c >> 2][16 * (c & 3)]) = rb[q];
+    }
+  };
+
+  gload(0);
+  for (int64_t k0 = 0; k0 < np; k0 += BK) {
+    __syncthreads();
+    lstore();
+    __syncthreads();
+    if (k0 + BK < np) gload(k0 + BK);
+    v4i b[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) b[ct] = *(const v4i*)(&Bs[64 * wc + 16 * ct + (lane & 15)][16 * (lane >> 4)]);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const v4i a = *(const v4i*)(&As[p][32 * wr + 16 * rt + (lane & 15)][16 * (lane >> 4)]);
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) acc[rt][ct][p] = mfma_i8(a, b[ct], acc[rt][ct][p]);
+      }
+  }
+
+  const int64_t ss = snp_stride(PL);
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int cl = 64 * wc + 16 * ct + (lane & 15);  // column within the tile
+    const int64_t col = n0 + cl;
+    double* st = sstat + col * ss;
+    double v[PL];
+#pragma unroll
+    for (int a = 0; a < PL; ++a) v[a] = st[a];
+    double mx = 0.0;
+    double ps[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) ps[q] = 0.0;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+      const int64_t kb = m0 + 32 * wr + 16 * rt + 4 * (lane >> 4);
+      double xs[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t k = kb + r;
+        double x = (((double)acc[rt][ct][0][r] * 256.0 + (double)acc[rt][ct][1][r]) * 256.0 +
+                    (double)acc[rt][ct][2][r]) * 256.0 + (double)acc[rt][ct][3][r];
+        x *= zs[k];
+#pragma unroll
+        for (int a = 0; a < PL; ++a) x -= Qt[k + a * np] * v[a];
+        xs[r] = x;
+        if (EPI == 0) {
+          mx = fmax(mx, fabs(x));
+        } else {
+#pragma unroll
+          for (int l = 0; l <= PL; ++l) ps[l] += V[l * np + k] * x;
+          ps[PL + 1] += Dv[k] * x * x;
+        }
+      }
+      if (EPI == 0) *(v4d*)(X + col * np + kb) = (v4d){xs[0], xs[1], xs[2], xs[3]};
+    }
+    if (EPI == 0) {
+      mx = fmax(mx, __shfl_xor(mx, 16, 64));
+      mx = fmax(mx, __shfl_xor(mx, 32, 64));
+      if ((lane >> 4) == 0 && col < mb)
+        atomicMax((unsigned long long*)(st + 2 * PL + 2), (unsigned long long)__double_as_longlong(mx));
+    } else {
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        double s = ps[q] + __shfl_xor(ps[q], 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        if ((lane >> 4) == 0) Ps[(wr * BN + cl) * NP + q] = s;
+      }
+    }
+  }
+  if (EPI == 1) {
+    __syncthreads();
+    // the two row halves of the tile combine (fixed order); one partial per
+    // (row tile, SNP)
+    for (int e = tid; e < BN * NP; e += 256) {
+      const int cl = e / NP, q = e % NP;
+      part[((int64_t)blockIdx.x * mbp + n0 + cl) * NP + q] = Ps[cl * NP + q] + Ps[(BN + cl) * NP + q];
+    }
+  }
+}
+
+// Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
+// order and solves the cell (Schur complement, FP64).
+template <int PL>
+__global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp,
+                                                const double* __restrict__ part, const double* __restrict__ tpar,
+                                                const double* __restrict__ sstat, uint32_t flags,
+                                                void* __restrict__ ob, void* __restrict__ ose, int out_f64,
+                                                int64_t ldo, uint8_t* __restrict__ oflags) {
+  constexpr int NP = PL + 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m_blk) return;
+  double s[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) s[q] = 0.0;
+  for (int64_t rt = 0; rt < nrt; ++rt) {
+    const double* pp = part + (rt * mbp + i) * NP;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) s[q] += pp[q];
+  }
+  schur_store<PL>(s, s[PL], s[PL + 1], tpar, sstat + i * snp_stride(PL), flags, i, 0, ob, ose, out_f64, ldo,
+                  oflags);
+}
+
+// Digit encoding of the rotated SNPs for the grid contraction: x with scale
+// max_k |x_k|, x o x with scale (max_k |x_k|)^2, four planes each, four
+// consecutive eigen rows per thread.
+__global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double* __restrict__ X,
+                                               const double* __restrict__ sstat, int8_t* __restrict__ Xd,
+                                               int64_t xplane) {
+  const int64_t i = blockIdx.y;
+  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (k >= np) return;
+  const double mx = sstat[i * snp_stride(pL) + 2 * pL + 2];
+  const double inv = mx > 0.0 ? 1.0 / mx : 0.0, inv2 = inv * inv;
+  const v4d x = *(const v4d*)(X + i * np + k);
+  int32_t pk[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    int8_t d[4], e[4];
+    digits4(quantize(x[r], inv), d);
+    digits4(quantize(x[r] * x[r], inv2), e);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      pk[q] |= ((int32_t)(uint8_t)d[q]) << (8 * r);
+      pk[4 + q] |= ((int32_t)(uint8_t)e[q]) << (8 * r);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + i * np + k) = pk[q];
+}
+
+hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
+  const int64_t m_pad = roundup(m_blk, SNP_PAD);
+  const Workspace& W = p.ws;
+  dim3 grid((unsigned)(p.n_pad / 64), (unsigned)(m_pad / 128));
+  if (p.fused_t1) {
+#define CLAK_R1(PLV)                                                                                         \
+  case PLV:                                                                                                  \
+    k_rot_i8<PLV, 1><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
+                                                 nullptr, W.V64, W.D64, W.part);                             \
+    break;
+    switch (p.pL) {
+      CLAK_R1(1) CLAK_R1(2) CLAK_R1(3) CLAK_R1(4) CLAK_R1(5) CLAK_R1(6) CLAK_R1(7) CLAK_R1(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef CLAK_R1
+    return hipGetLastError();
+  }
+#define CLAK_R0(PLV)                                                                                            \
+  case PLV:                                                                                                     \
+    k_rot_i8<PLV, 0><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, W.X64, \
+                                                 nullptr, nullptr, nullptr);                                    \
+    break;
+  switch (p.pL) {
+    CLAK_R0(1) CLAK_R0(2) CLAK_R0(3) CLAK_R0(4) CLAK_R0(5) CLAK_R0(6) CLAK_R0(7) CLAK_R0(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CLAK_R0
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  dim3 qgrid((unsigned)((p.n_pad / 4 + 255) / 256), (unsigned)roundup(m_blk, 64));
+  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, (int)p.pL, W.X64, W.sstat, W.Xd, p.mb_pad * p.n_pad);
+  return hipGetLastError();
+}
+// ------------------------------------------------------------------ grid
+//
+// The inner loop of the multi-trait CLAK-Eig listing for a tile of 64 SNPs x
+// 16 traits: W_R^T W_L, W_R^T Y_j and W_R^T W_R become, with the per-trait
+// operand of the trait kernel, c' = V_c^T x, r' = (D e)^T x and a = d^T (x o x).
+// x (4 planes) multiplies the 16 (PL+1) operand columns, x o x (4 planes) the
+// 16 d columns.  Digit products are grouped by total weight g = a + b <= 3
+// into four exact int32 accumulators.
+template <int PL>
+__global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int64_t t, const int8_t* __restrict__ Xd,
+                                                 int64_t xplane, const int8_t* __restrict__ Vd,
+                                                 int64_t vplane, const int8_t* __restrict__ Dd, int64_t dplane,
+                                                 const double* __restrict__ vs, const double* __restrict__ ds,
+                                                 const double* __restrict__ tpar, const double* __restrict__ sstat,
+                                                 uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
+                                                 int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
+  constexpr int NCV = 16 * (PL + 1), NC = NCV + 16, NCT = NC / 16, BK = 64;
+  constexpr int A_BYTES = 8 * 64 * LROW, B_BYTES = 4 * NC * LROW;
+  constexpr int C_BYTES = 16 * (NC + 1) * 8;
+  constexpr int SMEM = (A_BYTES + B_BYTES) > C_BYTES ? (A_BYTES + B_BYTES) : C_BYTES;
+  __shared__ __attribute__((aligned(16))) int8_t smem[SMEM];
+  int8_t(*As)[64][LROW] = (int8_t(*)[64][LROW])smem;             // [8][64][LROW]
+  int8_t(*Bs)[NC][LROW] = (int8_t(*)[NC][LROW])(smem + A_BYTES);  // [4][NC][LROW]
+  double(*Cs)[NC + 1] = (double(*)[NC + 1])smem;                  // [16][NC+1]
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 16;
+
+  v4i acc[NCT][4];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[c][g] = (v4i){0, 0, 0, 0};
+
+  for (int64_t k0 = 0; k0 < np; k0 += BK) {
+    // A: 8 planes x 64 SNPs x 64 bytes
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int c = tid + 256 * q;
+      const int pl = c >> 8, s = (c >> 2) & 63, kq = c & 3;
+      *(v4i*)(&As[pl][s][16 * kq]) = *(const v4i*)(Xd + pl * xplane + (i0 + s) * np + k0 + 16 * kq);
+    }
+    // B: 4 planes x NC columns x 64 bytes
+    for (int c = tid; c < 4 * NC * 4; c += 256) {
+      const int pl = c / (NC * 4), rem = c % (NC * 4), col = rem >> 2, kq = rem & 3;
+      const int8_t* src = (col < NCV) ? Vd + pl * vplane + (j0 * (PL + 1) + col) * np
+                                      : Dd + pl * dplane + (j0 + col - NCV) * np;
+      *(v4i*)(&Bs[pl][col][16 * kq]) = *(const v4i*)(src + k0 + 16 * kq);
+    }
+    __syncthreads();
+    v4i xa[4], xq[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      xa[p] = *(const v4i*)(&As[p][16 * wid + (lane & 15)][16 * (lane >> 4)]);
+      xq[p] = *(const v4i*)(&As[4 + p][16 * wid + (lane & 15)][16 * (lane >> 4)]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) {
+      v4i bv[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) bv[p] = *(const v4i*)(&Bs[p][16 * ct + (lane & 15)][16 * (lane >> 4)]);
+      const v4i* A = (ct < PL + 1) ? xa : xq;
+      acc[ct][0] = mfma_i8(A[0], bv[0], acc[ct][0]);
+      acc[ct][1] = mfma_i8(A[0], bv[1], acc[ct][1]);
+      acc[ct][1] = mfma_i8(A[1], bv[0], acc[ct][1]);
+      acc[ct][2] = mfma_i8(A[0], bv[2], acc[ct][2]);
+      acc[ct][2] = mfma_i8(A[1], bv[1], acc[ct][2]);
+      acc[ct][2] = mfma_i8(A[2], bv[0], acc[ct][2]);
+      acc[ct][3] = mfma_i8(A[0], bv[3], acc[ct][3]);
+      acc[ct][3] = mfma_i8(A[1], bv[2], acc[ct][3]);
+      acc[ct][3] = mfma_i8(A[2], bv[1], acc[ct][3]);
+      acc[ct][3] = mfma_i8(A[3], bv[0], acc[ct][3]);
+    }
+    __syncthreads();
+  }
+
+  // epilogue: values in FP64 through LDS, one wave's 16 SNPs at a time
+  const int64_t ss = snp_stride(PL);
+  for (int w = 0; w < 4; ++w) {
+    if (wid == w) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + 16 * w + 4 * (lane >> 4) + r;
+        const double gs = sstat[i * ss + 2 * PL + 2];  // max_k |x~_k| of SNP i
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+          const int c = 16 * ct + (lane & 15);
+          const double S = (((double)acc[ct][0][r] * 256.0 + (double)acc[ct][1][r]) * 256.0 + (double)acc[ct][2][r]) *
+                               256.0 + (double)acc[ct][3][r];
+          const double scale = (c < NCV) ? gs * vs[j0 * (PL + 1) + c] : gs * gs * ds[j0 + c - NCV];
+          Cs[4 * (lane >> 4) + r][c] = S * scale * (1.0 / 127.0);
+        }
+      }
+    }
+    __syncthreads();
+    {
+      const int s = tid & 15, jj = tid >> 4;
+      const int64_t i = i0 + 16 * w + s, j = j0 + jj;
+      if (i < m_blk && j < t) {
+        double c[PL];
+#pragma unroll
+        for (int l = 0; l < PL; ++l) c[l] = Cs[s][jj * (PL + 1) + l];
+        const double r = Cs[s][jj * (PL + 1) + PL];
+        const double a = Cs[s][NCV + jj];
+        schur_store<PL>(c, r, a, tpar + j * trait_stride(PL), sstat + i * ss, flags, i, j, ob, ose, out_f64, ldo,
+                        oflags);
+      }
+    }
+    __syncthreads();
+  }
+}
 
 hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                              uint8_t* d_flags) {
-  return hipErrorNotSupported;
+  const int f64 = out_dtype == CLAK_OUT_F64;
+  const Workspace& W = p.ws;
+  if (p.fused_t1) {
+    dim3 fgrid((unsigned)((m_blk + 255) / 256));
+#define CLAK_F1(PLV)                                                                                          \
+  case PLV:                                                                                                   \
+    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(p.n_pad / 64, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, \
+                                               d_b, d_se, f64, ldo, d_flags);                                 \
+    break;
+    switch (p.pL) {
+      CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef CLAK_F1
+    return hipGetLastError();
+  }
+  dim3 grid((unsigned)((m_blk + 63) / 64), (unsigned)(p.t_pad / 16));
+  const int64_t xplane = p.mb_pad * p.n_pad, vplane = p.t_pad * (p.pL + 1) * p.n_pad, dplane = p.t_pad * p.n_pad;
+#define CLAK_GI8(PLV)                                                                                              \
+  case PLV:                                                                                                        \
+    k_grid_i8<PLV><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.t, W.Xd, xplane, W.Vd, vplane, W.Dd, dplane, W.vs, \
+                                               W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, ldo, d_flags);      \
+    break;
+  switch (p.pL) {
+    CLAK_GI8(1) CLAK_GI8(2) CLAK_GI8(3) CLAK_GI8(4) CLAK_GI8(5) CLAK_GI8(6) CLAK_GI8(7) CLAK_GI8(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CLAK_GI8
+  return hipGetLastError();
 }
 
 }  // namespace clak

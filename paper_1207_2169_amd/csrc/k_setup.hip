@@ -171,20 +171,16 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
   auto zero_fill = [&]() {
     for (int64_t k = threadIdx.x; k < np; k += blockDim.x) {
       for (int l = 0; l < ncol; ++l) {
-        if (MIXED) {
+        if (Vd)
           for (int q = 0; q < 4; ++q) Vd[q * vplane + (j * ncol + l) * np + k] = 0;
-        } else {
-          V64[(j * ncol + l) * np + k] = 0.0;
-        }
+        if (V64) V64[(j * ncol + l) * np + k] = 0.0;
       }
-      if (MIXED) {
+      if (Dd)
         for (int q = 0; q < 4; ++q) Dd[q * dplane + j * np + k] = 0;
-      } else {
-        D64[j * np + k] = 0.0;
-      }
+      if (D64) D64[j * np + k] = 0.0;
     }
     if (threadIdx.x == 0) {
-      if (MIXED) {
+      if (vs) {
         for (int l = 0; l < ncol; ++l) vs[j * ncol + l] = 0.0;
         ds[j] = 0.0;
       }
@@ -338,7 +334,7 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
       for (int l = 0; l < ncol; ++l) V64[(j * ncol + l) * np + k] = v[l];
       D64[j * np + k] = v[ncol];
     }
-  } else {
+  } else if (Vd) {
     // column maxima, then the digit planes of every column
     for (int l = 0; l < ncol + 1; ++l) {
       double mx = 0.0;
@@ -371,13 +367,21 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
       ds[j] = cmax[ncol] / QMAX;
     }
   }
+  if (MIXED && V64) {  // FP64 copy for the fused single-trait kernel
+    for (int64_t k = threadIdx.x; k < np; k += blockDim.x) {
+      double v[MAX_PL + 2];
+      column_values(k, v);
+      for (int l = 0; l < ncol; ++l) V64[(j * ncol + l) * np + k] = v[l];
+      D64[j * np + k] = v[ncol];
+    }
+  }
 }
 
 hipError_t launch_traits(const Plan& p) {
   const Workspace& W = p.ws;
   if (p.prec == CLAK_PREC_MIXED)
     k_traits<true><<<dim3((unsigned)p.t_pad), 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, p.t, p.t_pad, W.w, W.XLt,
-                                                                  W.Yt, W.tpar, nullptr, nullptr, W.Vd, W.Dd, W.vs,
+                                                                  W.Yt, W.tpar, W.V64, W.D64, W.Vd, W.Dd, W.vs,
                                                                   W.ds, W.dstat);
   else
     k_traits<false><<<dim3((unsigned)p.t_pad), 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, p.t, p.t_pad, W.w,
