@@ -89,6 +89,7 @@ typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_pre
 /* Per-cell flag values written by clak_run_block. */
 #define CLAK_CELL_OK 0
 #define CLAK_CELL_DEGENERATE 1  /* g_i in span(X_L) (or numerically so): b and SE are NaN */
+#define CLAK_CELL_BAD_GENOTYPE 2 /* a genotype of the SNP is not 0, 1 or 2: b and SE are NaN */
 
 typedef struct clak_plan_s* clak_plan_t;
 
@@ -158,6 +159,24 @@ clak_status clak_set_traits(clak_plan_t plan, const double* d_Y, int64_t ldy,
 clak_status clak_run_block(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype,
                            int64_t ldg, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                            uint8_t* d_flags);
+
+/* Stages of clak_run_block timed by the profiler. */
+#define CLAK_STAGE_INGEST 0  /* genotype block -> int8 panel, per-SNP centring statistics */
+#define CLAK_STAGE_ROTATE 1  /* X~ = Z^T G (plus the fused single-trait reduction)      */
+#define CLAK_STAGE_ENCODE 2  /* digit encoding of X~ for the grid (mixed, several traits) */
+#define CLAK_STAGE_GRID 3    /* grid contraction + Schur solve, or the single-trait finish */
+#define CLAK_STAGE_COUNT 4
+
+/* Turns per-stage timing on (enable != 0) or off and clears the
+ * accumulators.  While on, clak_run_block brackets each stage's kernel with
+ * HIP events on the plan's stream (a little host overhead per launch). */
+clak_status clak_plan_set_profiling(clak_plan_t plan, int enable);
+
+/* Waits for the plan's stream, then returns per stage the summed kernel time
+ * in milliseconds (ms[CLAK_STAGE_COUNT]) and the number of launches timed
+ * (launches[CLAK_STAGE_COUNT]) since profiling was last enabled.  Either
+ * array may be NULL. */
+clak_status clak_plan_get_profile(clak_plan_t plan, double* ms, int64_t* launches);
 
 /* Destroys the plan (host memory, rocBLAS handle).  Never frees the workspace. */
 clak_status clak_plan_destroy(clak_plan_t plan);

@@ -33,6 +33,8 @@ CLAK_OUT_SNP, CLAK_OUT_FULL = 0, 2
 CLAK_G_U8, CLAK_G_F16 = 0, 1
 CLAK_OUT_F32, CLAK_OUT_F64 = 0, 1
 CLAK_CELL_OK, CLAK_CELL_DEGENERATE, CLAK_CELL_BAD_GENOTYPE = 0, 1, 2
+CLAK_STAGE_INGEST, CLAK_STAGE_ROTATE, CLAK_STAGE_ENCODE, CLAK_STAGE_GRID, CLAK_STAGE_COUNT = 0, 1, 2, 3, 4
+STAGE_NAMES = ("ingest", "rotate", "encode", "grid")
 
 # exported symbol -> (restype, argtypes)
 _P, _I64, _I, _U32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
@@ -47,6 +49,8 @@ SIGNATURES = {
     "clak_set_traits": (_I, [_P, _P, _I64, _P, _P]),
     "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
     "clak_plan_destroy": (_I, [_P]),
+    "clak_plan_set_profiling": (_I, [_P, _I]),
+    "clak_plan_get_profile": (_I, [_P, _P, _P]),
     "clak_last_error": (ctypes.c_char_p, []),
     "clak_version": (ctypes.c_char_p, []),
 }
@@ -181,6 +185,18 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
         fptr = flags.data_ptr()
     _check(lib().clak_run_block(plan, m, G.data_ptr(), gdt, G.stride(0), b.data_ptr(), se.data_ptr(), odt, ldo,
                                 fptr), "clak_run_block")
+
+
+def clak_plan_set_profiling(plan: int, enable: bool = True):
+    _check(lib().clak_plan_set_profiling(plan, 1 if enable else 0), "clak_plan_set_profiling")
+
+
+def clak_plan_get_profile(plan: int):
+    """{stage name: (total ms, launches)} since profiling was enabled."""
+    ms = (ctypes.c_double * CLAK_STAGE_COUNT)()
+    n = (ctypes.c_int64 * CLAK_STAGE_COUNT)()
+    _check(lib().clak_plan_get_profile(plan, ctypes.cast(ms, _P), ctypes.cast(n, _P)), "clak_plan_get_profile")
+    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
 
 
 def clak_plan_destroy(plan: int):

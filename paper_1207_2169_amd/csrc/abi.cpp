@@ -51,6 +51,33 @@ clak_status need_state(const Plan* p, int min_state, const char* what) {
 
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
+hipEvent_t take_event(Plan* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Waits for every timed stage, adds its duration, recycles the events.
+clak_status drain_profile(Plan* p) {
+  if (p->pending.empty()) return CLAK_OK;
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (auto& t : p->pending) {
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    p->stage_ms[t.stage] += ms;
+    p->stage_n[t.stage] += 1;
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  p->pending.clear();
+  return CLAK_OK;
+}
+
 clak_status sync_and_read_status(Plan* p) {
   HIP_TRY(hipMemcpyAsync(p->hstat, p->ws.dstat, sizeof(int) * DS_COUNT, hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -89,16 +116,13 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
     W.V64 = (double*)take(8 * tp * (pl + 1) * np);
     W.D64 = (double*)take(8 * tp * np);
   }
-  if (p.prec == CLAK_PREC_FP64) {
-    W.X64 = (double*)take(8 * mb * np);
-  } else if (p.fused_t1) {
+  if (p.fused_t1) W.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
+  if (!p.fused_t1) W.X64 = (double*)take(8 * mb * np);
+  if (p.prec == CLAK_PREC_MIXED) {
     W.Zd = (int8_t*)take(4 * np * np);
     W.zs = (double*)take(8 * np);
-    W.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
-  } else {
-    W.Zd = (int8_t*)take(4 * np * np);
-    W.zs = (double*)take(8 * np);
-    W.X64 = (double*)take(8 * mb * np);
+  }
+  if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) {
     W.Xd = (int8_t*)take(8 * mb * np);
     W.Vd = (int8_t*)take(4 * tp * (pl + 1) * np);
     W.Dd = (int8_t*)take(4 * tp * np);
@@ -144,7 +168,7 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   p->n_pad = roundup(n, KPAD);
   p->mb_pad = roundup(max_block, SNP_PAD);
   p->t_pad = roundup(t, TRAIT_PAD);
-  p->fused_t1 = (precision == CLAK_PREC_MIXED && t == 1);
+  p->fused_t1 = (t == 1);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(CLAK_E_DEVICE, "plan_create: no HIP device");
@@ -318,15 +342,58 @@ clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_
   const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
   if (!aligned(d_b, esz) || !aligned(d_se, esz)) return fail(CLAK_E_ARG, "run_block: misaligned output");
   if (g_dtype == CLAK_G_F16 && !aligned(d_G, 2)) return fail(CLAK_E_ARG, "run_block: misaligned F16 genotypes");
-  HIP_TRY(launch_ingest(*p, m_blk, d_G, g_dtype, ldg));
-  HIP_TRY(launch_rotate_snps(*p, m_blk));
-  HIP_TRY(launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags));
+  auto staged = [&](int stage, auto&& launch) -> hipError_t {
+    if (!p->profiling) return launch();
+    hipEvent_t a = take_event(p), b = take_event(p);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, p->stream);
+    if (e == hipSuccess) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(b, p->stream);
+    p->pending.push_back({stage, a, b});
+    return e;
+  };
+  HIP_TRY(staged(CLAK_STAGE_INGEST, [&] { return launch_ingest(*p, m_blk, d_G, g_dtype, ldg); }));
+  HIP_TRY(staged(CLAK_STAGE_ROTATE, [&] { return launch_rotate_snps(*p, m_blk); }));
+  if (p->prec == CLAK_PREC_MIXED && !p->fused_t1)
+    HIP_TRY(staged(CLAK_STAGE_ENCODE, [&] { return launch_encode(*p, m_blk); }));
+  HIP_TRY(staged(CLAK_STAGE_GRID, [&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); }));
+  return ok();
+}
+
+clak_status clak_plan_set_profiling(clak_plan_t h, int enable) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_set_profiling: null plan");
+  clak_status s = drain_profile(p);
+  if (s) return s;
+  for (int i = 0; i < CLAK_STAGE_COUNT; ++i) {
+    p->stage_ms[i] = 0.0;
+    p->stage_n[i] = 0;
+  }
+  p->profiling = enable != 0;
+  return ok();
+}
+
+clak_status clak_plan_get_profile(clak_plan_t h, double* ms, int64_t* launches) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_get_profile: null plan");
+  clak_status s = drain_profile(p);
+  if (s) return s;
+  for (int i = 0; i < CLAK_STAGE_COUNT; ++i) {
+    if (ms) ms[i] = p->stage_ms[i];
+    if (launches) launches[i] = p->stage_n[i];
+  }
   return ok();
 }
 
 clak_status clak_plan_destroy(clak_plan_t h) {
   Plan* p = as_plan(h);
   if (!p) return fail(CLAK_E_ARG, "plan_destroy: null plan");
+  if (!p->pending.empty()) (void)hipStreamSynchronize(p->stream);
+  for (auto& t : p->pending) {
+    p->event_pool.push_back(t.a);
+    p->event_pool.push_back(t.b);
+  }
+  for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
   if (p->rocblas) rocblas_destroy_handle((rocblas_handle)p->rocblas);
   if (p->hstat) (void)hipHostFree(p->hstat);
   delete p;

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/clak.h"
 
@@ -70,7 +71,7 @@ struct Workspace {
   // FP64 per-trait operand (FP64 path; mixed path when the fused t = 1 kernel runs)
   double* V64 = nullptr;    // t_pad*(pL+1) x n_pad: per-trait operand columns (row = column)
   double* D64 = nullptr;    // t_pad x n_pad: d_j
-  double* part = nullptr;   // fused t = 1 kernel: (n_pad/64) x mb_pad x (pL+2) partial sums
+  double* part = nullptr;   // fused t = 1 kernel: [n_pad/64][pL+2][mb_pad] partial sums
   // mixed path
   int8_t* Zd = nullptr;     // 4 planes x n_pad x n_pad: digits of Z^T rows
   double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
@@ -95,7 +96,17 @@ struct Plan {
   size_t ws_bytes = 0;
   Workspace ws;
   int state = ST_CREATED;
-  bool fused_t1 = false;    // mixed path with a single trait: rotate-and-reduce kernel
+  bool fused_t1 = false;    // single trait: rotate-and-reduce kernel, no stored X~
+  // stage profiler: pending (stage, start, end) event triples and totals
+  bool profiling = false;
+  struct Timed {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> event_pool;
+  double stage_ms[CLAK_STAGE_COUNT] = {0, 0, 0, 0};
+  int64_t stage_n[CLAK_STAGE_COUNT] = {0, 0, 0, 0};
   int* hstat = nullptr;     // pinned host mirror of dstat
 };
 
@@ -112,6 +123,9 @@ hipError_t launch_check_eigen(const Plan& p);
 // per block
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);
 hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);
+hipError_t launch_encode(const Plan& p, int64_t m_blk);
+hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                         uint8_t* d_flags);
 hipError_t launch_grid(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                        uint8_t* d_flags);
 

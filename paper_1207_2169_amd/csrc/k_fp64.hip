@@ -15,14 +15,22 @@ namespace clak {
 //   MODE 1: B = int8 SNP panel Gp (row = SNP, ld np); the centring
 //           x = C[k][col] - sum_a (Z^T Q_L)[k][a] v_a(col) is fused and the
 //           result stored SNP-major: out[col * np + k].
+//   MODE 2: as MODE 1, but with a single trait the cell sums of the tile's
+//           64 rows (c' against the whitened covariate columns, r' against
+//           D e, a = d^T (x o x)) are formed in FP64 and written as one partial
+//           per (row tile, SNP), part[(blockIdx.x * (pL+2) + q) * mbp + col];
+//           the rotated SNPs are not stored.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_rot64(int64_t n, int64_t np, int pL, const double* __restrict__ Zt,
                                                const void* __restrict__ B, int64_t ldb, int64_t ncols,
                                                double* __restrict__ out, int64_t ldo, const double* __restrict__ Qt,
-                                               const double* __restrict__ sstat) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+                                               const double* __restrict__ sstat, const double* __restrict__ V,
+                                               const double* __restrict__ Dv, double* __restrict__ part,
+                                               int64_t mbp) {
+  constexpr int BM = 64, BN = 64, BK = 16, NPM = MAX_PL + 2;
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
+  __shared__ double Ps[MODE == 2 ? 2 * BN * NPM : 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
   const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
@@ -68,6 +76,42 @@ __global__ void __launch_bounds__(256) k_rot64(int64_t n, int64_t np, int pL, co
     __syncthreads();
   }
   const int64_t ss = snp_stride(pL);
+  if (MODE == 2) {
+    const int NP = pL + 2;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int cl = 32 * wc + 16 * j + (lane & 15);
+      const double* st = sstat + (n0 + cl) * ss;
+      double ps[NPM];
+#pragma unroll
+      for (int q = 0; q < NPM; ++q) ps[q] = 0.0;
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + 32 * wr + 16 * i + 4 * r + (lane >> 4);
+          double x = acc[i][j][r];
+          for (int a = 0; a < pL; ++a) x -= Qt[row + a * np] * st[a];
+#pragma unroll
+          for (int q = 0; q < NPM - 1; ++q)
+            if (q <= pL) ps[q] += V[q * np + row] * x;
+          ps[NPM - 1] += Dv[row] * x * x;
+        }
+#pragma unroll
+      for (int q = 0; q < NPM; ++q) {
+        double v = ps[q] + __shfl_xor(ps[q], 16, 64);
+        v += __shfl_xor(v, 32, 64);
+        const int qq = (q == NPM - 1) ? NP - 1 : q;
+        if ((lane >> 4) == 0 && (q <= pL || q == NPM - 1)) Ps[(wr * BN + cl) * NPM + qq] = v;
+      }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < BN * NP; e += 256) {
+      const int cl = e % BN, q = e / BN;
+      part[((int64_t)blockIdx.x * NP + q) * mbp + n0 + cl] = Ps[cl * NPM + q] + Ps[(BN + cl) * NPM + q];
+    }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -94,15 +138,20 @@ hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64
                               int64_t ldo) {
   dim3 grid((unsigned)(p.n_pad / 64), (unsigned)((ncols + 63) / 64));
   k_rot64<0><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, p.ws.Zt, B, ldb, ncols, out, ldo, nullptr,
-                                         nullptr);
+                                         nullptr, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t launch_rotate_snps_fp64(const Plan& p, int64_t m_blk) {
   const int64_t m_pad = roundup(m_blk, 64);
   dim3 grid((unsigned)(p.n_pad / 64), (unsigned)(m_pad / 64));
-  k_rot64<1><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, p.ws.Zt, p.ws.Gp, p.n_pad, m_pad, p.ws.X64,
-                                         p.n_pad, p.ws.Qt, p.ws.sstat);
+  const Workspace& W = p.ws;
+  if (p.fused_t1)
+    k_rot64<2><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.n_pad, m_pad, nullptr, 0, W.Qt,
+                                           W.sstat, W.V64, W.D64, W.part, p.mb_pad);
+  else
+    k_rot64<1><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.n_pad, m_pad, W.X64, p.n_pad,
+                                           W.Qt, W.sstat, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
@@ -178,6 +227,7 @@ __global__ void __launch_bounds__(256) k_grid64(int64_t np, int64_t m_blk, int64
 
 hipError_t launch_grid_fp64(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                             uint8_t* d_flags) {
+  if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
   dim3 grid((unsigned)((m_blk + 63) / 64), (unsigned)(p.t_pad / 16));
   const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;

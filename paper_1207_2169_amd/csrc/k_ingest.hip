@@ -8,108 +8,161 @@
 
 namespace clak {
 
-// One wave per SPW SNPs; lanes stride over the individuals.  Per SNP g:
+// A work-group takes 64 SNPs (one per lane).  The individuals are walked in
+// windows of 128; in each window wave w handles individuals [16w, 16w + 16)
+// of every lane's SNP, and the window's 128 rows of Q_L are staged in LDS
+// (read back as wave-uniform broadcasts).  Per SNP g:
 //   v = Q_L^T g, gg = g^T g, res = gg - ||v||^2 = ||g - Q_L v||^2,
 //   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
 //   (gg == 0 or res <= 1e-10 gg); else 0.
 // SNP rows in [m_blk, m_pad) are written as zero SNPs with flag 1.
-template <int PLMAX, int SPW, bool F16>
-__global__ void __launch_bounds__(256) k_ingest(int64_t n, int64_t np, int pL, int64_t m_blk, int64_t m_pad,
-                                                const void* __restrict__ G, int64_t ldg,
-                                                const double* __restrict__ QL, const double* __restrict__ Rinv,
-                                                int8_t* __restrict__ Gp, double* __restrict__ sstat) {
+// ALIGN is the byte alignment shared by G and its leading dimension (u8).
+constexpr int ING_WAVES = 8;
+
+template <int PL, int ALIGN, bool F16>
+__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np, int64_t m_blk,
+                                                           int64_t m_pad, const void* __restrict__ G, int64_t ldg,
+                                                           const double* __restrict__ QL,
+                                                           const double* __restrict__ Rinv, int8_t* __restrict__ Gp,
+                                                           double* __restrict__ sstat) {
+  constexpr int NV = PL + 2;  // v, gg, bad
+  constexpr int WIN = 16 * ING_WAVES;
+  __shared__ double red[ING_WAVES][64][NV + 1];
+  __shared__ __attribute__((aligned(16))) double qs[PL][WIN];
   const int lane = threadIdx.x & 63;
-  const int64_t snp0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPW;
-  if (snp0 >= m_pad) return;
-  double acc[SPW][PLMAX];
-  double gg[SPW];
-  int bad[SPW];
+  const int wid = threadIdx.x >> 6;
+  const int64_t snp = (int64_t)blockIdx.x * 64 + lane;
+  double acc[PL];
 #pragma unroll
-  for (int s = 0; s < SPW; ++s) {
-    gg[s] = 0.0;
-    bad[s] = 0;
+  for (int a = 0; a < PL; ++a) acc[a] = 0.0;
+  double gg = 0.0;
+  int bad = 0;
+  for (int64_t w0 = 0; w0 < np; w0 += WIN) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < PL * WIN; e += 64 * ING_WAVES) qs[e / WIN][e % WIN] = QL[w0 + e % WIN + (e / WIN) * np];
+    const int64_t i0 = w0 + 16 * wid;
+    uint8_t by[16];
 #pragma unroll
-    for (int a = 0; a < PLMAX; ++a) acc[s][a] = 0.0;
-  }
-  for (int64_t i = lane; i < np; i += 64) {
-    double q[PLMAX];
+    for (int e = 0; e < 16; ++e) by[e] = 0;
+    if (snp < m_blk) {
+      if (F16) {
+        const __half* row = (const __half*)G + snp * ldg + i0;
 #pragma unroll
-    for (int a = 0; a < PLMAX; ++a) q[a] = (a < pL) ? QL[i + a * np] : 0.0;
-#pragma unroll
-    for (int s = 0; s < SPW; ++s) {
-      const int64_t snp = snp0 + s;
-      if (snp >= m_pad) break;
-      int g = 0;
-      if (snp < m_blk && i < n) {
-        if (F16) {
-          const float f = __half2float(((const __half*)G)[snp * ldg + i]);
-          g = (int)f;
-          if (!(f == 0.0f || f == 1.0f || f == 2.0f)) bad[s] = 1;
+        for (int e = 0; e < 16; ++e)
+          if (i0 + e < n) {
+            const float f = __half2float(row[e]);
+            by[e] = (f == 0.0f || f == 1.0f || f == 2.0f) ? (uint8_t)f : 3;
+          }
+      } else {
+        const uint8_t* row = (const uint8_t*)G + snp * ldg + i0;
+        if (i0 + 16 <= n) {
+          __builtin_memcpy(by, __builtin_assume_aligned(row, ALIGN), 16);
         } else {
-          g = ((const uint8_t*)G)[snp * ldg + i];
-          if (g > 2) bad[s] = 1;
+#pragma unroll
+          for (int e = 0; e < 16; ++e) by[e] = (i0 + e < n) ? row[e] : 0;
         }
-        if (bad[s]) g = 0;
       }
-      Gp[snp * np + i] = (int8_t)g;
-      const double gd = (double)g;
-      gg[s] += gd * gd;
+    }
+    double gd[16];
 #pragma unroll
-      for (int a = 0; a < PLMAX; ++a) acc[s][a] += q[a] * gd;
+    for (int e = 0; e < 16; ++e) {
+      if (by[e] > 2) {
+        bad = 1;
+        by[e] = 0;
+      }
+      gd[e] = (double)by[e];
+      gg += gd[e] * gd[e];
+    }
+    if (snp < m_pad) __builtin_memcpy(__builtin_assume_aligned(Gp + snp * np + i0, 16), by, 16);
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < PL; ++a) {
+      const double* src = &qs[a][16 * wid];
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int e = 0; e < 16; e += 2) {
+        s0 += src[e] * gd[e];
+        s1 += src[e + 1] * gd[e + 1];
+      }
+      acc[a] += s0 + s1;
     }
   }
-  const int64_t ss = snp_stride(pL);
 #pragma unroll
-  for (int s = 0; s < SPW; ++s) {
-    const int64_t snp = snp0 + s;
-    double v[PLMAX];
+  for (int a = 0; a < PL; ++a) red[wid][lane][a] = acc[a];
+  red[wid][lane][PL] = gg;
+  red[wid][lane][PL + 1] = (double)bad;
+  __syncthreads();
+  if (wid != 0 || snp >= m_pad) return;
+  double v[PL];
 #pragma unroll
-    for (int a = 0; a < PLMAX; ++a) v[a] = wave_sum(acc[s][a]);
-    const double g2 = wave_sum(gg[s]);
-    int b = bad[s];
+  for (int a = 0; a < PL; ++a) v[a] = 0.0;
+  double g2 = 0.0, b = 0.0;
+  for (int w = 0; w < ING_WAVES; ++w) {
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) b |= __shfl_xor(b, o, 64);
-    if (lane == 0 && snp < m_pad) {
-      double vv = 0.0;
-      for (int a = 0; a < pL; ++a) vv += v[a] * v[a];
-      const double res = g2 - vv;
-      int flag = b ? 2 : ((snp >= m_blk || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
-      double* st = sstat + snp * ss;
-      for (int a = 0; a < pL; ++a) {
-        double gam = 0.0;
-        for (int c = a; c < pL; ++c) gam += Rinv[a * pL + c] * v[c];
-        st[a] = flag ? 0.0 : v[a];
-        st[pL + a] = flag ? 0.0 : gam;
-      }
-      st[2 * pL] = flag ? 1.0 : sqrt(res);
-      st[2 * pL + 1] = (double)flag;
-      st[2 * pL + 2] = 0.0;
-    }
+    for (int a = 0; a < PL; ++a) v[a] += red[w][lane][a];
+    g2 += red[w][lane][PL];
+    b += red[w][lane][PL + 1];
   }
+  double vv = 0.0;
+#pragma unroll
+  for (int a = 0; a < PL; ++a) vv += v[a] * v[a];
+  const double res = g2 - vv;
+  const int flag = b > 0.0 ? 2 : ((snp >= m_blk || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
+  const int64_t ss = snp_stride(PL);
+  double* st = sstat + snp * ss;
+#pragma unroll
+  for (int a = 0; a < PL; ++a) {
+    double gam = 0.0;
+#pragma unroll
+    for (int c = a; c < PL; ++c) gam += Rinv[a * PL + c] * v[c];
+    st[a] = flag ? 0.0 : v[a];
+    st[PL + a] = flag ? 0.0 : gam;
+  }
+  st[2 * PL] = flag ? 1.0 : sqrt(res);
+  st[2 * PL + 1] = (double)flag;
+  st[2 * PL + 2] = 0.0;
+}
+
+template <int PL>
+static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const void* d_G, int g_dtype, int64_t ldg) {
+  dim3 grid((unsigned)(m_pad / 64));
+  const Workspace& W = p.ws;
+  const dim3 block(64 * ING_WAVES);
+  if (g_dtype == CLAK_G_F16) {
+    k_ingest<PL, 1, true><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, d_G, ldg, W.QL, W.Rinv, W.Gp,
+                                                        W.sstat);
+    return;
+  }
+  // widest alignment shared by the base address and the row pitch, capped at 16
+  const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
+  const int align = (int)(bits & (~bits + 1));
+#define CLAK_ING(A)                                                                                           \
+  k_ingest<PL, A, false><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, d_G, ldg, W.QL, W.Rinv, W.Gp, \
+                                                       W.sstat)
+  if (align >= 16)
+    CLAK_ING(16);
+  else if (align >= 8)
+    CLAK_ING(8);
+  else if (align >= 4)
+    CLAK_ING(4);
+  else
+    CLAK_ING(1);
+#undef CLAK_ING
 }
 
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg) {
   const int64_t m_pad = roundup(m_blk, SNP_PAD);
-  const int pL = (int)p.pL;
-  const bool f16 = g_dtype == CLAK_G_F16;
-#define CLAK_INGEST(PLM, SPW)                                                                                 \
-  do {                                                                                                        \
-    const int64_t per_block = 4 * SPW;                                                                        \
-    dim3 grid((unsigned)((m_pad + per_block - 1) / per_block));                                               \
-    if (f16)                                                                                                  \
-      k_ingest<PLM, SPW, true><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, pL, m_blk, m_pad, d_G, ldg, p.ws.QL, \
-                                                           p.ws.Rinv, p.ws.Gp, p.ws.sstat);                   \
-    else                                                                                                      \
-      k_ingest<PLM, SPW, false><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, pL, m_blk, m_pad, d_G, ldg,         \
-                                                            p.ws.QL, p.ws.Rinv, p.ws.Gp, p.ws.sstat);         \
-  } while (0)
-  if (pL <= 4)
-    CLAK_INGEST(4, 8);
-  else if (pL <= 8)
-    CLAK_INGEST(8, 4);
-  else
-    CLAK_INGEST(16, 2);
-#undef CLAK_INGEST
+  switch (p.pL) {
+#define CLAK_ID(PLV)                                          \
+  case PLV:                                                   \
+    ingest_dispatch<PLV>(p, m_blk, m_pad, d_G, g_dtype, ldg); \
+    break;
+    CLAK_ID(1) CLAK_ID(2) CLAK_ID(3) CLAK_ID(4) CLAK_ID(5) CLAK_ID(6) CLAK_ID(7) CLAK_ID(8)
+    CLAK_ID(9) CLAK_ID(10) CLAK_ID(11) CLAK_ID(12) CLAK_ID(13) CLAK_ID(14) CLAK_ID(15) CLAK_ID(16)
+#undef CLAK_ID
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

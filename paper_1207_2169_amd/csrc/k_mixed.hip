@@ -25,28 +25,37 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 //
 // Step 3 of the multi-trait CLAK-Eig listing on one SNP block, X~ = Z^T G:
 // a 64 (eigen rows) x 128 (SNPs) tile per work-group, four waves of 32 x 64,
-// four digit planes of Z^T against the same genotype fragment.  Per element,
-// the planes are recombined exactly in FP64, scaled, and the centring term
-// (Z^T Q_L)[k] . v(i) is subtracted.  Then
+// four digit planes of Z^T against the same genotype fragment, LDS double
+// buffered (one barrier per 64-deep K slice, the next slice's global loads in
+// flight during the current slice's MFMAs).  Tiles are ordered so that the
+// work-groups of one XCD walk the row tiles of the same SNP columns, which
+// keeps that genotype panel in the XCD's L2.
+// Per element, the planes are recombined exactly in FP64, scaled, and the
+// centring term (Z^T Q_L)[k] . v(i) is subtracted.  Then
 //   EPI 0: the FP64 value is stored (SNP-major) and the SNP's max |x~_k| is
 //          raised by an atomic max, for the digit encoding of the grid operand;
 //   EPI 1: (single trait) the cell sums c', r', a of this tile's 64 rows are
 //          formed in FP64 against the FP64 trait operand and written as one
 //          partial per (row tile, SNP); x~ never leaves the chip.
 template <int PL, int EPI>
-__global__ void __launch_bounds__(256) k_rot_i8(int64_t np, int64_t mb, int64_t mbp, const int8_t* __restrict__ Zd,
-                                                const double* __restrict__ zs, const int8_t* __restrict__ Gp,
-                                                const double* __restrict__ Qt, double* __restrict__ sstat,
-                                                double* __restrict__ X, const double* __restrict__ V,
-                                                const double* __restrict__ Dv, double* __restrict__ part) {
+__global__ void __launch_bounds__(256, (EPI == 1 && PL > 5) ? 1 : 2) k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn,
+                                                   const int8_t* __restrict__ Zd, const double* __restrict__ zs,
+                                                   const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
+                                                   double* __restrict__ sstat, double* __restrict__ X,
+                                                   const double* __restrict__ V, const double* __restrict__ Dv,
+                                                   double* __restrict__ part) {
   constexpr int BM = 64, BN = 128, BK = 64, NP = PL + 2;
-  __shared__ __attribute__((aligned(16))) int8_t As[4][BM][LROW];
-  __shared__ __attribute__((aligned(16))) int8_t Bs[BN][LROW];
-  __shared__ double Ps[EPI == 1 ? 2 * BN * NP : 1];
+  constexpr int A_STAGE = 4 * BM * LROW, B_STAGE = BN * LROW;
+  __shared__ __attribute__((aligned(16))) int8_t smem[2 * (A_STAGE + B_STAGE)];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid >> 1, wc = wid & 1;
-  const int64_t m0 = (int64_t)blockIdx.x * BM, n0 = (int64_t)blockIdx.y * BN;
+  const int64_t ntm = np / BM, ntiles = ntm * ntn;
+  const int64_t per_xcd = (ntiles + 7) / 8;
+  const int64_t T = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (T >= ntiles) return;
+  const int64_t m0 = (T % ntm) * BM, n0 = (T / ntm) * BN;
   const int64_t zplane = np * np;
+  const int KT = (int)(np / BK);
 
   v4i acc[2][4][4];
 #pragma unroll
@@ -56,95 +65,152 @@ __global__ void __launch_bounds__(256) k_rot_i8(int64_t np, int64_t mb, int64_t 
 #pragma unroll
       for (int p = 0; p < 4; ++p) acc[i][j][p] = (v4i){0, 0, 0, 0};
 
-  // global -> register staging of the next K slice, then register -> LDS
   v4i ra[4], rb[2];
-  auto gload = [&](int64_t k0) {
+  auto gload = [&](int kt) {
+    const int64_t k0 = (int64_t)kt * BK;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {  // plane q, row tid/4, 16-byte chunk tid%4
+    for (int q = 0; q < 4; ++q)  // plane q, row tid/4, 16-byte chunk tid%4
       ra[q] = *(const v4i*)(Zd + q * zplane + (m0 + (tid >> 2)) * np + k0 + 16 * (tid & 3));
-    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int c = tid + 256 * q;
       rb[q] = *(const v4i*)(Gp + (n0 + (c >> 2)) * np + k0 + 16 * (c & 3));
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
+    int8_t* As = smem + buf * A_STAGE;
+    int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *(v4i*)(&As[q][tid >> 2][16 * (tid & 3)]) = ra[q];
+    for (int q = 0; q < 4; ++q) *(v4i*)(As + (q * BM + (tid >> 2)) * LROW + 16 * (tid & 3)) = ra[q];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int c = tid + 256 * q;
-      *(v4i*)(&Bs[c >> 2][16 * (c & 3)]) = rb[q];
+      *(v4i*)(Bs + (c >> 2) * LROW + 16 * (c & 3)) = rb[q];
     }
   };
 
   gload(0);
-  for (int64_t k0 = 0; k0 < np; k0 += BK) {
-    __syncthreads();
-    lstore();
-    __syncthreads();
-    if (k0 + BK < np) gload(k0 + BK);
+  lstore(0);
+  __syncthreads();
+  if (KT > 1) gload(1);
+  for (int kt = 0; kt < KT; ++kt) {
+    const int buf = kt & 1;
+    const int8_t* As = smem + buf * A_STAGE;
+    const int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
     v4i b[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) b[ct] = *(const v4i*)(&Bs[64 * wc + 16 * ct + (lane & 15)][16 * (lane >> 4)]);
+    for (int ct = 0; ct < 4; ++ct)
+      b[ct] = *(const v4i*)(Bs + (64 * wc + 16 * ct + (lane & 15)) * LROW + 16 * (lane >> 4));
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt)
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const v4i a = *(const v4i*)(&As[p][32 * wr + 16 * rt + (lane & 15)][16 * (lane >> 4)]);
+        const v4i a = *(const v4i*)(As + (p * BM + 32 * wr + 16 * rt + (lane & 15)) * LROW + 16 * (lane >> 4));
 #pragma unroll
         for (int ct = 0; ct < 4; ++ct) acc[rt][ct][p] = mfma_i8(a, b[ct], acc[rt][ct][p]);
       }
+    if (kt + 1 < KT) {
+      lstore(buf ^ 1);
+      if (kt + 2 < KT) gload(kt + 2);
+    }
+    __syncthreads();
   }
 
+  // epilogue tables in LDS (the staging buffers are free after the last barrier)
+  double* Qs = (double*)smem;              // [BM][PL]   (Z^T Q_L) rows of the tile
+  double* zS = Qs + BM * PL;               // [BM]       digit scales of Z^T rows
+  double* vS = zS + BM;                    // [BN][PL]   centring coefficients of the SNPs
+  double* Vs = vS + BN * PL;               // [BM][NP]   trait operand rows (EPI 1)
+  double* Ps = Vs + BM * NP;               // [2][BN][NP] row-half partial sums (EPI 1)
   const int64_t ss = snp_stride(PL);
+  for (int e = tid; e < BM * PL; e += 256) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
+  for (int e = tid; e < BM; e += 256) zS[e] = zs[m0 + e];
+  for (int e = tid; e < BN * PL; e += 256) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
+  if (EPI == 1)
+    for (int e = tid; e < BM * NP; e += 256) {
+      const int r = e / NP, q = e % NP;
+      Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
+    }
+  __syncthreads();
+
+  // Row-outer epilogue over groups of CG columns: each of the lane's 8 rows
+  // reads its table entries once per group and serves the group's columns.
+  // The four digit-plane sums are first paired exactly in int32 (|sum| <
+  // 2^23 for n_pad <= 32768).
+  constexpr int CG = (EPI == 0) ? 4 : 1;
 #pragma unroll
-  for (int ct = 0; ct < 4; ++ct) {
-    const int cl = 64 * wc + 16 * ct + (lane & 15);  // column within the tile
-    const int64_t col = n0 + cl;
-    double* st = sstat + col * ss;
-    double v[PL];
+  for (int cg = 0; cg < 4; cg += CG) {
+    double vcol[CG][PL];
 #pragma unroll
-    for (int a = 0; a < PL; ++a) v[a] = st[a];
-    double mx = 0.0;
-    double ps[NP];
+    for (int c = 0; c < CG; ++c)
 #pragma unroll
-    for (int q = 0; q < NP; ++q) ps[q] = 0.0;
+      for (int a = 0; a < PL; ++a) vcol[c][a] = vS[(64 * wc + 16 * (cg + c) + (lane & 15)) * PL + a];
+    double ps[CG][NP];
+    double mx[CG];
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      mx[c] = 0.0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) ps[c][q] = 0.0;
+    }
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-      const int64_t kb = m0 + 32 * wr + 16 * rt + 4 * (lane >> 4);
-      double xs[4];
+      const int rb0 = 32 * wr + 16 * rt + 4 * (lane >> 4);  // row within the tile
+      double xs[CG][4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t k = kb + r;
-        double x = (((double)acc[rt][ct][0][r] * 256.0 + (double)acc[rt][ct][1][r]) * 256.0 +
-                    (double)acc[rt][ct][2][r]) * 256.0 + (double)acc[rt][ct][3][r];
-        x *= zs[k];
+        const int rr = rb0 + r;
+        const double z = zS[rr];
+        double qrow[PL];
 #pragma unroll
-        for (int a = 0; a < PL; ++a) x -= Qt[k + a * np] * v[a];
-        xs[r] = x;
-        if (EPI == 0) {
-          mx = fmax(mx, fabs(x));
-        } else {
+        for (int a = 0; a < PL; ++a) qrow[a] = Qs[rr * PL + a];
+        double vrow[NP];
+        if (EPI == 1) {
 #pragma unroll
-          for (int l = 0; l <= PL; ++l) ps[l] += V[l * np + k] * x;
-          ps[PL + 1] += Dv[k] * x * x;
+          for (int q = 0; q < NP; ++q) vrow[q] = Vs[rr * NP + q];
+        }
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+          const int ct = cg + c;
+          const int hi = acc[rt][ct][0][r] * 256 + acc[rt][ct][1][r];
+          const int lo = acc[rt][ct][2][r] * 256 + acc[rt][ct][3][r];
+          double x = fma((double)hi, 65536.0, (double)lo) * z;
+#pragma unroll
+          for (int a = 0; a < PL; ++a) x -= qrow[a] * vcol[c][a];
+          xs[c][r] = x;
+          if (EPI == 0) {
+            mx[c] = fmax(mx[c], fabs(x));
+          } else {
+#pragma unroll
+            for (int q = 0; q <= PL; ++q) ps[c][q] += vrow[q] * x;
+            ps[c][PL + 1] += vrow[PL + 1] * x * x;
+          }
         }
       }
-      if (EPI == 0) *(v4d*)(X + col * np + kb) = (v4d){xs[0], xs[1], xs[2], xs[3]};
-    }
-    if (EPI == 0) {
-      mx = fmax(mx, __shfl_xor(mx, 16, 64));
-      mx = fmax(mx, __shfl_xor(mx, 32, 64));
-      if ((lane >> 4) == 0 && col < mb)
-        atomicMax((unsigned long long*)(st + 2 * PL + 2), (unsigned long long)__double_as_longlong(mx));
-    } else {
+      if (EPI == 0) {
 #pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        double s = ps[q] + __shfl_xor(ps[q], 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        if ((lane >> 4) == 0) Ps[(wr * BN + cl) * NP + q] = s;
+        for (int c = 0; c < CG; ++c) {
+          const int64_t col = n0 + 64 * wc + 16 * (cg + c) + (lane & 15);
+          *(v4d*)(X + col * np + m0 + rb0) = (v4d){xs[c][0], xs[c][1], xs[c][2], xs[c][3]};
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < CG; ++c) {
+      const int cl = 64 * wc + 16 * (cg + c) + (lane & 15);
+      const int64_t col = n0 + cl;
+      if (EPI == 0) {
+        double m = fmax(mx[c], __shfl_xor(mx[c], 16, 64));
+        m = fmax(m, __shfl_xor(m, 32, 64));
+        if ((lane >> 4) == 0 && col < mb)
+          atomicMax((unsigned long long*)(sstat + col * ss + 2 * PL + 2), (unsigned long long)__double_as_longlong(m));
+      } else {
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          double v = ps[c][q] + __shfl_xor(ps[c][q], 16, 64);
+          v += __shfl_xor(v, 32, 64);
+          if ((lane >> 4) == 0) Ps[(wr * BN + cl) * NP + q] = v;
+        }
       }
     }
   }
@@ -152,15 +218,17 @@ __global__ void __launch_bounds__(256) k_rot_i8(int64_t np, int64_t mb, int64_t 
     __syncthreads();
     // the two row halves of the tile combine (fixed order); one partial per
     // (row tile, SNP)
+    const int64_t rtile = m0 / BM;
     for (int e = tid; e < BN * NP; e += 256) {
-      const int cl = e / NP, q = e % NP;
-      part[((int64_t)blockIdx.x * mbp + n0 + cl) * NP + q] = Ps[cl * NP + q] + Ps[(BN + cl) * NP + q];
+      const int cl = e % BN, q = e / BN;
+      part[(rtile * NP + q) * mbp + n0 + cl] = Ps[cl * NP + q] + Ps[(BN + cl) * NP + q];
     }
   }
 }
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
-// order and solves the cell (Schur complement, FP64).
+// order and solves the cell (Schur complement, FP64).  A work-group takes 64
+// SNPs; its four waves sum interleaved row tiles, then wave 0 adds the four.
 template <int PL>
 __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp,
                                                 const double* __restrict__ part, const double* __restrict__ tpar,
@@ -168,16 +236,23 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
                                                 void* __restrict__ ob, void* __restrict__ ose, int out_f64,
                                                 int64_t ldo, uint8_t* __restrict__ oflags) {
   constexpr int NP = PL + 2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m_blk) return;
+  __shared__ double red[4][64][NP + 1];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + lane;
   double s[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) s[q] = 0.0;
-  for (int64_t rt = 0; rt < nrt; ++rt) {
-    const double* pp = part + (rt * mbp + i) * NP;
+  if (i < m_blk)
+    for (int64_t rt = wid; rt < nrt; rt += 4) {
 #pragma unroll
-    for (int q = 0; q < NP; ++q) s[q] += pp[q];
-  }
+      for (int q = 0; q < NP; ++q) s[q] += part[(rt * NP + q) * mbp + i];
+    }
+#pragma unroll
+  for (int q = 0; q < NP; ++q) red[wid][lane][q] = s[q];
+  __syncthreads();
+  if (wid != 0 || i >= m_blk) return;
+#pragma unroll
+  for (int q = 0; q < NP; ++q) s[q] = ((red[0][lane][q] + red[1][lane][q]) + red[2][lane][q]) + red[3][lane][q];
   schur_store<PL>(s, s[PL], s[PL + 1], tpar, sstat + i * snp_stride(PL), flags, i, 0, ob, ose, out_f64, ldo,
                   oflags);
 }
@@ -213,12 +288,13 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double*
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   const int64_t m_pad = roundup(m_blk, SNP_PAD);
   const Workspace& W = p.ws;
-  dim3 grid((unsigned)(p.n_pad / 64), (unsigned)(m_pad / 128));
+  const int64_t ntn = m_pad / 128, ntiles = (p.n_pad / 64) * ntn;
+  dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
   if (p.fused_t1) {
-#define CLAK_R1(PLV)                                                                                         \
-  case PLV:                                                                                                  \
-    k_rot_i8<PLV, 1><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
-                                                 nullptr, W.V64, W.D64, W.part);                             \
+#define CLAK_R1(PLV)                                                                                              \
+  case PLV:                                                                                                       \
+    k_rot_i8<PLV, 1><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
+                                                 nullptr, W.V64, W.D64, W.part);                                  \
     break;
     switch (p.pL) {
       CLAK_R1(1) CLAK_R1(2) CLAK_R1(3) CLAK_R1(4) CLAK_R1(5) CLAK_R1(6) CLAK_R1(7) CLAK_R1(8)
@@ -228,10 +304,10 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
 #undef CLAK_R1
     return hipGetLastError();
   }
-#define CLAK_R0(PLV)                                                                                            \
-  case PLV:                                                                                                     \
-    k_rot_i8<PLV, 0><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, W.X64, \
-                                                 nullptr, nullptr, nullptr);                                    \
+#define CLAK_R0(PLV)                                                                                              \
+  case PLV:                                                                                                       \
+    k_rot_i8<PLV, 0><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
+                                                 W.X64, nullptr, nullptr, nullptr);                               \
     break;
   switch (p.pL) {
     CLAK_R0(1) CLAK_R0(2) CLAK_R0(3) CLAK_R0(4) CLAK_R0(5) CLAK_R0(6) CLAK_R0(7) CLAK_R0(8)
@@ -239,10 +315,13 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
       return hipErrorInvalidValue;
   }
 #undef CLAK_R0
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_encode(const Plan& p, int64_t m_blk) {
+  if (p.prec != CLAK_PREC_MIXED || p.fused_t1) return hipSuccess;
   dim3 qgrid((unsigned)((p.n_pad / 4 + 255) / 256), (unsigned)roundup(m_blk, 64));
-  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, (int)p.pL, W.X64, W.sstat, W.Xd, p.mb_pad * p.n_pad);
+  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, (int)p.pL, p.ws.X64, p.ws.sstat, p.ws.Xd, p.mb_pad * p.n_pad);
   return hipGetLastError();
 }
 // ------------------------------------------------------------------ grid
@@ -356,25 +435,31 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
   }
 }
 
-hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                             uint8_t* d_flags) {
+hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                         uint8_t* d_flags) {
   const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;
-  if (p.fused_t1) {
-    dim3 fgrid((unsigned)((m_blk + 255) / 256));
+  dim3 fgrid((unsigned)((m_blk + 63) / 64));
 #define CLAK_F1(PLV)                                                                                          \
   case PLV:                                                                                                   \
     k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(p.n_pad / 64, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, \
                                                d_b, d_se, f64, ldo, d_flags);                                 \
     break;
-    switch (p.pL) {
-      CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)
-      default:
-        return hipErrorInvalidValue;
-    }
-#undef CLAK_F1
-    return hipGetLastError();
+  switch (p.pL) {
+    CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)
+    CLAK_F1(9) CLAK_F1(10) CLAK_F1(11) CLAK_F1(12) CLAK_F1(13) CLAK_F1(14) CLAK_F1(15) CLAK_F1(16)
+    default:
+      return hipErrorInvalidValue;
   }
+#undef CLAK_F1
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                             uint8_t* d_flags) {
+  const int f64 = out_dtype == CLAK_OUT_F64;
+  const Workspace& W = p.ws;
+  if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
   dim3 grid((unsigned)((m_blk + 63) / 64), (unsigned)(p.t_pad / 16));
   const int64_t xplane = p.mb_pad * p.n_pad, vplane = p.t_pad * (p.pL + 1) * p.n_pad, dplane = p.t_pad * p.n_pad;
 #define CLAK_GI8(PLV)                                                                                              \

@@ -81,3 +81,19 @@ def test_eigenbasis_invariance():
     b1, se1, _ = gpu_run(w, clak.CLAK_PREC_FP64, block=40, eigen=(Z * flip, ev))
     eb, es = errors(b1.ravel(), se1.ravel(), b0.ravel(), se0.ravel())
     assert eb < TOL and es < TOL
+
+
+@pytest.mark.parametrize("kw,block", [(dict(n=600, m=300, t=1, kin_cols=1200), 128),
+                                      (dict(n=700, m=200, t=40, kin_cols=1400), 200)])
+def test_eight_covariates(kw, block):
+    """p_L = 8 (intercept, sex, age, five principal components of Phi)."""
+    from paper_1207_2169_amd import clak
+    w = make_workload(4, **kw)
+    print(f"FP64 p_L=8 n={w.n} m={w.m} t={w.t}", flush=True)
+    b, se, fl = gpu_run(w, clak.CLAK_PREC_FP64, block=block)
+    ii, jj = _all_cells(w.m, w.t)
+    rb, rse, rfl = oracle_cells(w, ii, jj)
+    assert (fl == 0).all()
+    eb, es = errors(b.ravel(), se.ravel(), rb[:, -1], rse)
+    print(f"eps_b={eb:.3e} eps_se={es:.3e}")
+    assert eb < TOL and es < TOL

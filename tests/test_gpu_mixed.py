@@ -25,6 +25,8 @@ def _all_cells(m, t):
     (0, dict(), 2000),
     (2, dict(n=300, m=333, t=37, kin_cols=600), 200),
     (2, dict(n=1000, m=150, t=20), 150),
+    (4, dict(n=600, m=300, t=1, kin_cols=1200), 128),
+    (4, dict(n=700, m=200, t=40, kin_cols=1400), 200),
 ])
 def test_mixed_vs_oracle(cfg, kw, block):
     from paper_1207_2169_amd import clak
