@@ -160,6 +160,53 @@ clak_status clak_run_block(clak_plan_t plan, int64_t m_blk, const void* d_G, int
                            int64_t ldg, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                            uint8_t* d_flags);
 
+/* One SNP block of a pipeline or batch: the arguments of clak_run_block. */
+typedef struct clak_block {
+  int64_t m_blk;    /* SNPs in the block, 1 <= m_blk <= max_block        */
+  const void* G;    /* n x m_blk genotypes, leading dimension ldg        */
+  int64_t ldg;
+  void* b;          /* outputs as for clak_run_block, leading dimension ldo */
+  void* se;
+  int64_t ldo;
+  uint8_t* flags;   /* nullable */
+} clak_block;
+
+typedef struct clak_pipeline_s* clak_pipeline_t;
+typedef struct clak_batch_s* clak_batch_t;
+
+/* A reusable schedule of the per-block pipeline of `plan` over n_blocks
+ * blocks (the same arithmetic as n_blocks calls of clak_run_block).  Blocks
+ * alternate between two workspace slots so that the ingest of block b+1 runs
+ * on a side stream while block b is rotated and reduced on the main stream.
+ * The block arguments are validated and copied at creation; the buffers they
+ * point to must stay valid, and the plan must keep its workspace, while the
+ * pipeline is launched.  New traits (clak_set_traits) or covariates are picked
+ * up by later launches.  Creates two streams and a few events; no device work.
+ * Errors: as clak_run_block, CLAK_E_DEVICE. */
+clak_status clak_pipeline_create(clak_pipeline_t* pipe, clak_plan_t plan, int64_t n_blocks,
+                                 const clak_block* blocks, int g_dtype, int out_dtype);
+
+/* Enqueues the pipeline: forked from the plan's stream and joined back to it,
+ * so work later enqueued on the plan's stream runs after it (asynchronous). */
+clak_status clak_pipeline_launch(clak_pipeline_t pipe);
+
+/* Waits for the pipeline's streams and destroys them; frees no caller memory. */
+clak_status clak_pipeline_destroy(clak_pipeline_t pipe);
+
+/* Several cohorts in one submission: plans[k] (distinct plans, each READY, on
+ * the same device) runs its n_blocks[k] blocks, taken consecutively from
+ * `blocks`, as a pipeline on its own stream pair; the cohorts run
+ * concurrently, so the hardware scheduler balances cohorts of uneven n and t.
+ * Same lifetime rules as a pipeline. */
+clak_status clak_batch_create(clak_batch_t* batch, int n_plans, const clak_plan_t* plans, const int64_t* n_blocks,
+                              const clak_block* blocks, int g_dtype, int out_dtype);
+
+/* Enqueues the batch, forked from and joined back to hip_stream (may be NULL). */
+clak_status clak_batch_launch(clak_batch_t batch, void* hip_stream);
+
+/* Waits for the batch's streams and destroys them; frees no caller memory. */
+clak_status clak_batch_destroy(clak_batch_t batch);
+
 /* Stages of clak_run_block timed by the profiler. */
 #define CLAK_STAGE_INGEST 0  /* genotype block -> int8 panel, per-SNP centring statistics */
 #define CLAK_STAGE_ROTATE 1  /* X~ = Z^T G (plus the fused single-trait reduction)      */

@@ -55,6 +55,22 @@ SIGNATURES = {
     "clak_version": (ctypes.c_char_p, []),
 }
 
+class clak_block(ctypes.Structure):
+    _fields_ = [("m_blk", ctypes.c_int64), ("G", ctypes.c_void_p), ("ldg", ctypes.c_int64),
+                ("b", ctypes.c_void_p), ("se", ctypes.c_void_p), ("ldo", ctypes.c_int64),
+                ("flags", ctypes.c_void_p)]
+
+
+SIGNATURES.update({
+    "clak_pipeline_create": (_I, [ctypes.POINTER(_P), _P, _I64, ctypes.POINTER(clak_block), _I, _I]),
+    "clak_pipeline_launch": (_I, [_P]),
+    "clak_pipeline_destroy": (_I, [_P]),
+    "clak_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_I64),
+                               ctypes.POINTER(clak_block), _I, _I]),
+    "clak_batch_launch": (_I, [_P, _P]),
+    "clak_batch_destroy": (_I, [_P]),
+})
+
 _lib_handle = None
 
 
@@ -157,8 +173,27 @@ def clak_set_traits(plan: int, Y: torch.Tensor, h2: torch.Tensor, s2: torch.Tens
 
 
 def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
-                   flags: Optional[torch.Tensor] = None, m_blk: Optional[int] = None):
+                   flags: Optional[torch.Tensor] = None):
     """G: (m_blk, ldg) uint8 or float16 SNP rows; b, se: (t, ldo[, p]) float32/64."""
+    blk, gdt, odt = _block_args(G, b, se, flags)
+    _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags),
+           "clak_run_block")
+
+
+def clak_plan_set_profiling(plan: int, enable: bool = True):
+    _check(lib().clak_plan_set_profiling(plan, 1 if enable else 0), "clak_plan_set_profiling")
+
+
+def clak_plan_get_profile(plan: int):
+    """{stage name: (total ms, launches)} since profiling was enabled."""
+    ms = (ctypes.c_double * CLAK_STAGE_COUNT)()
+    n = (ctypes.c_int64 * CLAK_STAGE_COUNT)()
+    _check(lib().clak_plan_get_profile(plan, ctypes.cast(ms, _P), ctypes.cast(n, _P)), "clak_plan_get_profile")
+    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
+
+
+def _block_args(G, b, se, flags=None):
+    """(clak_block, g_dtype, out_dtype) for one block, with the checks of clak_run_block."""
     _dev(G, "G")
     if G.dtype == torch.uint8:
         gdt = CLAK_G_U8
@@ -168,7 +203,6 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
         raise ValueError("G must be uint8 or float16")
     if G.dim() != 2 or G.stride(1) != 1:
         raise ValueError("G must be 2-D with contiguous rows (one SNP per row)")
-    m = G.shape[0] if m_blk is None else m_blk
     _dev(b, "b")
     _dev(se, "se")
     if b.dtype != se.dtype or b.dtype not in (torch.float32, torch.float64):
@@ -183,20 +217,57 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
         if flags.shape != se.shape or flags.stride() != se.stride():
             raise ValueError("flags must match the layout of se")
         fptr = flags.data_ptr()
-    _check(lib().clak_run_block(plan, m, G.data_ptr(), gdt, G.stride(0), b.data_ptr(), se.data_ptr(), odt, ldo,
-                                fptr), "clak_run_block")
+    blk = clak_block(G.shape[0], G.data_ptr(), G.stride(0), b.data_ptr(), se.data_ptr(), ldo, fptr)
+    return blk, gdt, odt
 
 
-def clak_plan_set_profiling(plan: int, enable: bool = True):
-    _check(lib().clak_plan_set_profiling(plan, 1 if enable else 0), "clak_plan_set_profiling")
+def _block_array(blocks):
+    """blocks: sequence of (G, b, se[, flags]) -> ctypes array, g_dtype, out_dtype."""
+    items = [_block_args(*blk) for blk in blocks]
+    if not items:
+        raise ValueError("no blocks")
+    gdts = {it[1] for it in items}
+    odts = {it[2] for it in items}
+    if len(gdts) != 1 or len(odts) != 1:
+        raise ValueError("all blocks must share the genotype and output dtypes")
+    arr = (clak_block * len(items))(*[it[0] for it in items])
+    return arr, items[0][1], items[0][2]
 
 
-def clak_plan_get_profile(plan: int):
-    """{stage name: (total ms, launches)} since profiling was enabled."""
-    ms = (ctypes.c_double * CLAK_STAGE_COUNT)()
-    n = (ctypes.c_int64 * CLAK_STAGE_COUNT)()
-    _check(lib().clak_plan_get_profile(plan, ctypes.cast(ms, _P), ctypes.cast(n, _P)), "clak_plan_get_profile")
-    return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
+def clak_pipeline_create(plan: int, blocks) -> int:
+    """Graph-captured pipeline over blocks = [(G, b, se[, flags]), ...]."""
+    arr, gdt, odt = _block_array(blocks)
+    h = _P()
+    _check(lib().clak_pipeline_create(ctypes.byref(h), plan, len(arr), arr, gdt, odt), "clak_pipeline_create")
+    return h.value
+
+
+def clak_pipeline_launch(pipe: int):
+    _check(lib().clak_pipeline_launch(pipe), "clak_pipeline_launch")
+
+
+def clak_pipeline_destroy(pipe: int):
+    _check(lib().clak_pipeline_destroy(pipe), "clak_pipeline_destroy")
+
+
+def clak_batch_create(plans, blocks_per_plan) -> int:
+    """One graph over several plans; blocks_per_plan[k] = [(G, b, se[, flags]), ...]."""
+    flat = [blk for bl in blocks_per_plan for blk in bl]
+    arr, gdt, odt = _block_array(flat)
+    ph = (_P * len(plans))(*plans)
+    nb = (_I64 * len(plans))(*[len(bl) for bl in blocks_per_plan])
+    h = _P()
+    _check(lib().clak_batch_create(ctypes.byref(h), len(plans), ph, nb, arr, gdt, odt), "clak_batch_create")
+    return h.value
+
+
+def clak_batch_launch(batch: int, stream: Optional[torch.cuda.Stream] = None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().clak_batch_launch(batch, s.cuda_stream), "clak_batch_launch")
+
+
+def clak_batch_destroy(batch: int):
+    _check(lib().clak_batch_destroy(batch), "clak_batch_destroy")
 
 
 def clak_plan_destroy(plan: int):

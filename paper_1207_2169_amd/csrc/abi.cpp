@@ -13,7 +13,7 @@
 
 using namespace clak;
 
-namespace {
+namespace clak {
 
 thread_local std::string g_err;
 
@@ -39,6 +39,7 @@ clak_status ok() {
   } while (0)
 
 Plan* as_plan(clak_plan_t h) { return reinterpret_cast<Plan*>(h); }
+Plan* as_plan_public(clak_plan_t h) { return as_plan(h); }
 
 clak_status need_state(const Plan* p, int min_state, const char* what) {
   if (!p) return fail(CLAK_E_ARG, "%s: null plan", what);
@@ -84,10 +85,6 @@ clak_status sync_and_read_status(Plan* p) {
   return CLAK_OK;
 }
 
-}  // namespace
-
-namespace clak {
-
 // Carves the workspace.  With base == nullptr only the size is computed.
 size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   size_t off = 0;
@@ -110,24 +107,37 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   W.Qt = (double*)take(8 * np * pl);
   W.Yt = (double*)take(8 * np * p.t);
   W.tpar = (double*)take(8 * tp * trait_stride(p.pL));
-  W.Gp = (int8_t*)take(mb * np);
-  W.sstat = (double*)take(8 * mb * snp_stride(p.pL));
   if (p.prec == CLAK_PREC_FP64 || p.fused_t1) {
     W.V64 = (double*)take(8 * tp * (pl + 1) * np);
     W.D64 = (double*)take(8 * tp * np);
   }
-  if (p.fused_t1) W.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
-  if (!p.fused_t1) W.X64 = (double*)take(8 * mb * np);
   if (p.prec == CLAK_PREC_MIXED) {
     W.Zd = (int8_t*)take(4 * np * np);
     W.zs = (double*)take(8 * np);
   }
   if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) {
-    W.Xd = (int8_t*)take(8 * mb * np);
     W.Vd = (int8_t*)take(4 * tp * (pl + 1) * np);
     W.Dd = (int8_t*)take(4 * tp * np);
     W.vs = (double*)take(8 * tp * (pl + 1));
     W.ds = (double*)take(8 * tp);
+  }
+  for (int k = 0; k < NSLOTS; ++k) {
+    Slot& S = W.slot[k];
+    S.Gp = (int8_t*)take(mb * np);
+    S.sstat = (double*)take(8 * mb * snp_stride(p.pL));
+    S.ipart = (double*)take(8 * ING_MAX_SPLITS * (pl + 2) * mb);
+    if (p.fused_t1) S.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
+    if (!p.fused_t1) S.X64 = (double*)take(8 * mb * np);
+    if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) S.Xd = (int8_t*)take(8 * mb * np);
+  }
+  if (w) {
+    const Slot& S = W.slot[0];
+    W.Gp = S.Gp;
+    W.sstat = S.sstat;
+    W.ipart = S.ipart;
+    W.part = S.part;
+    W.X64 = S.X64;
+    W.Xd = S.Xd;
   }
   return off;
 }
@@ -325,11 +335,12 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   return ok();
 }
 
-clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
-                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags) {
-  Plan* p = as_plan(h);
-  clak_status s = need_state(p, ST_READY, "run_block");
-  if (s) return s;
+}  // extern "C"
+
+namespace clak {
+
+clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
+                           const void* d_se, int out_dtype, int64_t ldo) {
   if (m_blk < 1 || m_blk > p->max_block)
     return fail(CLAK_E_ARG, "run_block: m_blk=%lld outside [1, max_block=%lld]", (long long)m_blk,
                 (long long)p->max_block);
@@ -342,6 +353,16 @@ clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_
   const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
   if (!aligned(d_b, esz) || !aligned(d_se, esz)) return fail(CLAK_E_ARG, "run_block: misaligned output");
   if (g_dtype == CLAK_G_F16 && !aligned(d_G, 2)) return fail(CLAK_E_ARG, "run_block: misaligned F16 genotypes");
+  return CLAK_OK;
+}
+
+// Enqueues the per-block stages on the given streams (ingest on s_in, the
+// rest on s_main; the caller orders the two) using workspace slot `slot`.
+clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
+                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b, void* d_se,
+                          int out_dtype, int64_t ldo, uint8_t* d_flags) {
+  select_slot(*p, slot);
+  const hipStream_t saved = p->stream;
   auto staged = [&](int stage, auto&& launch) -> hipError_t {
     if (!p->profiling) return launch();
     hipEvent_t a = take_event(p), b = take_event(p);
@@ -352,11 +373,37 @@ clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_
     p->pending.push_back({stage, a, b});
     return e;
   };
-  HIP_TRY(staged(CLAK_STAGE_INGEST, [&] { return launch_ingest(*p, m_blk, d_G, g_dtype, ldg); }));
-  HIP_TRY(staged(CLAK_STAGE_ROTATE, [&] { return launch_rotate_snps(*p, m_blk); }));
-  if (p->prec == CLAK_PREC_MIXED && !p->fused_t1)
-    HIP_TRY(staged(CLAK_STAGE_ENCODE, [&] { return launch_encode(*p, m_blk); }));
-  HIP_TRY(staged(CLAK_STAGE_GRID, [&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); }));
+  hipError_t e;
+  p->stream = s_in;
+  e = staged(CLAK_STAGE_INGEST, [&] { return launch_ingest(*p, m_blk, d_G, g_dtype, ldg); });
+  if (e == hipSuccess && ingested) e = hipEventRecord(ingested, s_in);
+  if (e == hipSuccess && ingested && s_main != s_in) e = hipStreamWaitEvent(s_main, ingested, 0);
+  p->stream = s_main;
+  if (e == hipSuccess) e = staged(CLAK_STAGE_ROTATE, [&] { return launch_rotate_snps(*p, m_blk); });
+  if (e == hipSuccess && p->prec == CLAK_PREC_MIXED && !p->fused_t1)
+    e = staged(CLAK_STAGE_ENCODE, [&] { return launch_encode(*p, m_blk); });
+  if (e == hipSuccess)
+    e = staged(CLAK_STAGE_GRID, [&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); });
+  p->stream = saved;
+  select_slot(*p, 0);
+  if (e != hipSuccess) return fail(CLAK_E_DEVICE, "run_block: launch failed: %s", hipGetErrorString(e));
+  return CLAK_OK;
+}
+
+}  // namespace clak
+
+extern "C" {
+
+clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
+                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_READY, "run_block");
+  if (s) return s;
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo);
+  if (s) return s;
+  s = enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo,
+                    d_flags);
+  if (s) return s;
   return ok();
 }
 

@@ -16,9 +16,10 @@ namespace clak {
 // Padding of the individual / eigen-index axis (the contraction axis K of
 // every GEMM on the path) and of the SNP axis of a block.
 constexpr int64_t KPAD = 128;
-constexpr int64_t SNP_PAD = 128;
+constexpr int64_t SNP_PAD = 256;  // multiple of every SNP tile width
 constexpr int64_t TRAIT_PAD = 16;
 constexpr int MAX_PL = 16;
+constexpr int ING_MAX_SPLITS = 8;  // individual windows of the ingest are split over at most this many work-groups
 // int8 digit encoding: a value v with |v| <= s is stored as
 // q = rint(v / s * QMAX), |q| <= QMAX < 2^31, split into four base-256 digits.
 constexpr double QMAX = 2130706432.0;  // 127 * 2^24
@@ -50,7 +51,20 @@ enum DevStatus : int {
   DS_COUNT = 64
 };
 
+// Buffers of one SNP block in flight.  The workspace holds two such slots so
+// that a pipeline can ingest block b+1 while block b is rotated.
+struct Slot {
+  int8_t* Gp = nullptr;
+  double* sstat = nullptr;
+  double* ipart = nullptr;
+  double* part = nullptr;
+  double* X64 = nullptr;
+  int8_t* Xd = nullptr;
+};
+constexpr int NSLOTS = 2;
+
 struct Workspace {
+  Slot slot[NSLOTS];
   // common
   double* Zt = nullptr;     // n_pad x n_pad: row k (stride n_pad) = eigenvector k, zero padded
   double* w = nullptr;      // n_pad eigenvalues (zero beyond n)
@@ -63,9 +77,10 @@ struct Workspace {
   double* Qt = nullptr;     // n_pad x pL column-major: Z^T Q_L
   double* Yt = nullptr;     // n_pad x t  column-major: Z^T Y
   double* tpar = nullptr;   // t_pad x trait_stride
-  // per block
+  // per block (the slot selected for the block being launched)
   int8_t* Gp = nullptr;     // mb_pad x n_pad: SNP rows, individuals contiguous, zero padded
   double* sstat = nullptr;  // mb_pad x snp_stride
+  double* ipart = nullptr;  // ingest partials: [ING_MAX_SPLITS][pL+2][mb_pad]
   // rotated, centred SNPs in FP64 (both paths)
   double* X64 = nullptr;    // mb_pad x n_pad: row = SNP, eigen index contiguous
   // FP64 per-trait operand (FP64 path; mixed path when the fused t = 1 kernel runs)
@@ -111,6 +126,36 @@ struct Plan {
 };
 
 size_t workspace_bytes(const Plan& p, Workspace* carve, char* base);
+
+// Number of work-groups the ingest splits the individuals of one SNP group
+// over: one per 128-individual window, at most ING_MAX_SPLITS.  It depends on
+// n only, so every SNP's statistics are summed in the same order whatever the
+// block split.
+inline int ingest_splits(const Plan& p) {
+  const int64_t windows = p.n_pad / 128;
+  return (int)(windows < ING_MAX_SPLITS ? windows : ING_MAX_SPLITS);
+}
+
+// Points the per-block buffers of the workspace at slot k.
+inline void select_slot(Plan& p, int k) {
+  const Slot& s = p.ws.slot[k];
+  p.ws.Gp = s.Gp;
+  p.ws.sstat = s.sstat;
+  p.ws.ipart = s.ipart;
+  p.ws.part = s.part;
+  p.ws.X64 = s.X64;
+  p.ws.Xd = s.Xd;
+}
+
+// ---- ABI helpers (abi.cpp) ----
+clak_status fail(clak_status s, const char* fmt, ...);
+clak_status ok();
+clak_status need_state(const Plan* p, int min_state, const char* what);
+clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
+                           const void* d_se, int out_dtype, int64_t ldo);
+clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
+                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b, void* d_se,
+                          int out_dtype, int64_t ldo, uint8_t* d_flags);
 
 // ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
 // set-up

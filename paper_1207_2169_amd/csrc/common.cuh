@@ -10,6 +10,7 @@
 namespace clak {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double v) {

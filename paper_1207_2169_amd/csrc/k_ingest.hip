@@ -8,23 +8,20 @@
 
 namespace clak {
 
-// A work-group takes 64 SNPs (one per lane).  The individuals are walked in
-// windows of 128; in each window wave w handles individuals [16w, 16w + 16)
-// of every lane's SNP, and the window's 128 rows of Q_L are staged in LDS
-// (read back as wave-uniform broadcasts).  Per SNP g:
-//   v = Q_L^T g, gg = g^T g, res = gg - ||v||^2 = ||g - Q_L v||^2,
-//   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
-//   (gg == 0 or res <= 1e-10 gg); else 0.
-// SNP rows in [m_blk, m_pad) are written as zero SNPs with flag 1.
+// Pass 1.  A work-group takes 64 SNPs (one per lane) and the individual
+// windows s, s + S, s + 2S, ... (128 individuals each; blockIdx.y = s); in a
+// window wave w handles individuals [16w, 16w + 16) of every lane's SNP, and
+// the window's 128 rows of Q_L are staged in LDS (read back as wave-uniform
+// broadcasts).  The work-group writes the int8 panel rows of its windows and
+// one partial (Q_L^T g, g^T g, invalid-genotype count) per SNP.
 // ALIGN is the byte alignment shared by G and its leading dimension (u8).
 constexpr int ING_WAVES = 8;
 
 template <int PL, int ALIGN, bool F16>
-__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np, int64_t m_blk,
-                                                           int64_t m_pad, const void* __restrict__ G, int64_t ldg,
-                                                           const double* __restrict__ QL,
-                                                           const double* __restrict__ Rinv, int8_t* __restrict__ Gp,
-                                                           double* __restrict__ sstat) {
+__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np, int64_t m_blk, int64_t m_pad,
+                                                           int64_t mbp, const void* __restrict__ G, int64_t ldg,
+                                                           const double* __restrict__ QL, int8_t* __restrict__ Gp,
+                                                           double* __restrict__ ipart) {
   constexpr int NV = PL + 2;  // v, gg, bad
   constexpr int WIN = 16 * ING_WAVES;
   __shared__ double red[ING_WAVES][64][NV + 1];
@@ -32,12 +29,13 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
   const int64_t snp = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t S = gridDim.y, s0 = blockIdx.y;
   double acc[PL];
 #pragma unroll
   for (int a = 0; a < PL; ++a) acc[a] = 0.0;
   double gg = 0.0;
   int bad = 0;
-  for (int64_t w0 = 0; w0 < np; w0 += WIN) {
+  for (int64_t w0 = s0 * WIN; w0 < np; w0 += S * WIN) {
     __syncthreads();
     for (int e = threadIdx.x; e < PL * WIN; e += 64 * ING_WAVES) qs[e / WIN][e % WIN] = QL[w0 + e % WIN + (e / WIN) * np];
     const int64_t i0 = w0 + 16 * wid;
@@ -78,13 +76,13 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
 #pragma unroll
     for (int a = 0; a < PL; ++a) {
       const double* src = &qs[a][16 * wid];
-      double s0 = 0.0, s1 = 0.0;
+      double t0 = 0.0, t1 = 0.0;
 #pragma unroll
       for (int e = 0; e < 16; e += 2) {
-        s0 += src[e] * gd[e];
-        s1 += src[e + 1] * gd[e + 1];
+        t0 += src[e] * gd[e];
+        t1 += src[e + 1] * gd[e + 1];
       }
-      acc[a] += s0 + s1;
+      acc[a] += t0 + t1;
     }
   }
 #pragma unroll
@@ -93,29 +91,45 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
   red[wid][lane][PL + 1] = (double)bad;
   __syncthreads();
   if (wid != 0 || snp >= m_pad) return;
-  double v[PL];
 #pragma unroll
-  for (int a = 0; a < PL; ++a) v[a] = 0.0;
-  double g2 = 0.0, b = 0.0;
-  for (int w = 0; w < ING_WAVES; ++w) {
-#pragma unroll
-    for (int a = 0; a < PL; ++a) v[a] += red[w][lane][a];
-    g2 += red[w][lane][PL];
-    b += red[w][lane][PL + 1];
+  for (int q = 0; q < NV; ++q) {
+    double t = 0.0;
+    for (int w = 0; w < ING_WAVES; ++w) t += red[w][lane][q];
+    ipart[(s0 * NV + q) * mbp + snp] = t;
   }
+}
+
+// Pass 2, one thread per SNP: sums the S partials in a fixed order and writes
+//   v = Q_L^T g, gamma = R^{-1} v, ||g - Q_L v|| = sqrt(gg - ||v||^2), and
+//   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
+//   (gg == 0 or ||g - Q_L v||^2 <= 1e-10 gg); else 0.
+// SNP rows in [m_blk, m_pad) become zero SNPs with flag 1.
+template <int PL>
+__global__ void __launch_bounds__(256) k_ingest_fin(int64_t m_blk, int64_t m_pad, int64_t mbp, int S,
+                                                    const double* __restrict__ ipart, const double* __restrict__ Rinv,
+                                                    double* __restrict__ sstat) {
+  constexpr int NV = PL + 2;
+  const int64_t snp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (snp >= m_pad) return;
+  double t[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) t[q] = 0.0;
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) t[q] += ipart[(s * NV + q) * mbp + snp];
   double vv = 0.0;
 #pragma unroll
-  for (int a = 0; a < PL; ++a) vv += v[a] * v[a];
+  for (int a = 0; a < PL; ++a) vv += t[a] * t[a];
+  const double g2 = t[PL];
   const double res = g2 - vv;
-  const int flag = b > 0.0 ? 2 : ((snp >= m_blk || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
-  const int64_t ss = snp_stride(PL);
-  double* st = sstat + snp * ss;
+  const int flag = t[PL + 1] > 0.0 ? 2 : ((snp >= m_blk || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
+  double* st = sstat + snp * snp_stride(PL);
 #pragma unroll
   for (int a = 0; a < PL; ++a) {
     double gam = 0.0;
 #pragma unroll
-    for (int c = a; c < PL; ++c) gam += Rinv[a * PL + c] * v[c];
-    st[a] = flag ? 0.0 : v[a];
+    for (int c = a; c < PL; ++c) gam += Rinv[a * PL + c] * t[c];
+    st[a] = flag ? 0.0 : t[a];
     st[PL + a] = flag ? 0.0 : gam;
   }
   st[2 * PL] = flag ? 1.0 : sqrt(res);
@@ -125,29 +139,32 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
 
 template <int PL>
 static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const void* d_G, int g_dtype, int64_t ldg) {
-  dim3 grid((unsigned)(m_pad / 64));
+  const int S = ingest_splits(p);
+  dim3 grid((unsigned)(m_pad / 64), (unsigned)S);
   const Workspace& W = p.ws;
   const dim3 block(64 * ING_WAVES);
   if (g_dtype == CLAK_G_F16) {
-    k_ingest<PL, 1, true><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, d_G, ldg, W.QL, W.Rinv, W.Gp,
-                                                        W.sstat);
-    return;
-  }
-  // widest alignment shared by the base address and the row pitch, capped at 16
-  const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
-  const int align = (int)(bits & (~bits + 1));
-#define CLAK_ING(A)                                                                                           \
-  k_ingest<PL, A, false><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, d_G, ldg, W.QL, W.Rinv, W.Gp, \
-                                                       W.sstat)
-  if (align >= 16)
-    CLAK_ING(16);
-  else if (align >= 8)
-    CLAK_ING(8);
-  else if (align >= 4)
-    CLAK_ING(4);
-  else
-    CLAK_ING(1);
+    k_ingest<PL, 1, true><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
+                                                        W.ipart);
+  } else {
+    // widest alignment shared by the base address and the row pitch, capped at 16
+    const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
+    const int align = (int)(bits & (~bits + 1));
+#define CLAK_ING(A)                                                                                               \
+  k_ingest<PL, A, false><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, \
+                                                       W.ipart)
+    if (align >= 16)
+      CLAK_ING(16);
+    else if (align >= 8)
+      CLAK_ING(8);
+    else if (align >= 4)
+      CLAK_ING(4);
+    else
+      CLAK_ING(1);
 #undef CLAK_ING
+  }
+  k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv,
+                                                                        W.sstat);
 }
 
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg) {

@@ -23,57 +23,70 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 
 // ------------------------------------------------------------------ rotation
 //
-// Step 3 of the multi-trait CLAK-Eig listing on one SNP block, X~ = Z^T G:
-// a 64 (eigen rows) x 128 (SNPs) tile per work-group, four waves of 32 x 64,
-// four digit planes of Z^T against the same genotype fragment, LDS double
-// buffered (one barrier per 64-deep K slice, the next slice's global loads in
-// flight during the current slice's MFMAs).  Tiles are ordered so that the
-// work-groups of one XCD walk the row tiles of the same SNP columns, which
-// keeps that genotype panel in the XCD's L2.
-// Per element, the planes are recombined exactly in FP64, scaled, and the
-// centring term (Z^T Q_L)[k] . v(i) is subtracted.  Then
-//   EPI 0: the FP64 value is stored (SNP-major) and the SNP's max |x~_k| is
-//          raised by an atomic max, for the digit encoding of the grid operand;
-//   EPI 1: (single trait) the cell sums c', r', a of this tile's 64 rows are
+// Step 3 of the multi-trait CLAK-Eig listing on one SNP block, X~ = Z^T G.
+// A work-group of WR x WC waves takes a BM = 32 WR (eigen rows) x BN = 32 CT
+// WC (SNPs) tile; each wave owns 32 rows x CT 32-column MFMA tiles and all four
+// digit planes of Z^T for them (v_mfma_i32_32x32x32_i8), so one genotype
+// fragment feeds four MFMAs.  The K loop runs over 64-deep slices with LDS
+// double buffering (one barrier per slice; the next slice's global loads are
+// in flight during the current slice's MFMAs).  XCD x (work-groups are
+// dispatched round-robin over the 8 XCDs) owns a fixed slice of row tiles and
+// walks every SNP tile over it, so its slice of the Z^T digit planes stays in
+// that XCD's L2 while the genotype panel streams.
+// Per element, the planes are recombined exactly, scaled, and the centring
+// term (Z^T Q_L)[k] . v(i) is subtracted (FP64).  Then
+//   EPI 0: the value is stored (SNP-major) and the SNP's max |x~_k| is raised
+//          by an atomic max, for the digit encoding of the grid operand;
+//   EPI 1: (single trait) the cell sums c', r', a of this tile's rows are
 //          formed in FP64 against the FP64 trait operand and written as one
 //          partial per (row tile, SNP); x~ never leaves the chip.
-template <int PL, int EPI>
-__global__ void __launch_bounds__(256, (EPI == 1 && PL > 5) ? 1 : 2) k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn,
-                                                   const int8_t* __restrict__ Zd, const double* __restrict__ zs,
-                                                   const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
-                                                   double* __restrict__ sstat, double* __restrict__ X,
-                                                   const double* __restrict__ V, const double* __restrict__ Dv,
-                                                   double* __restrict__ part) {
-  constexpr int BM = 64, BN = 128, BK = 64, NP = PL + 2;
+//
+// v_mfma_i32_32x32x32_i8 lane layout (gfx950): lane l supplies 16 bytes of row
+// l%32 of A and of column l%32 of B, the same 16 values of the 32-deep
+// contraction (half l/32); result register r holds C[8(r/4) + 4(l/32) + r%4][l%32].
+__device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+template <int PL, int EPI, int CT, int WR, int WC>
+__global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5)) ? 1 : 2)
+    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, const int8_t* __restrict__ Zd,
+             const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
+             double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
+             const double* __restrict__ Dv, double* __restrict__ part) {
+  constexpr int NT = 64 * WR * WC, BM = 32 * WR, BN = 32 * CT * WC, BK = 64, NP = PL + 2;
   constexpr int A_STAGE = 4 * BM * LROW, B_STAGE = BN * LROW;
+  constexpr int A_LD = 16 * BM / NT, B_LD = 4 * BN / NT;  // 16-byte loads per thread per slice
+  static_assert(16 * BM % NT == 0 && 4 * BN % NT == 0, "tile / thread mismatch");
   __shared__ __attribute__((aligned(16))) int8_t smem[2 * (A_STAGE + B_STAGE)];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wr = wid >> 1, wc = wid & 1;
-  const int64_t ntm = np / BM, ntiles = ntm * ntn;
-  const int64_t per_xcd = (ntiles + 7) / 8;
-  const int64_t T = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (T >= ntiles) return;
-  const int64_t m0 = (T % ntm) * BM, n0 = (T / ntm) * BN;
+  const int wr = wid / WC, wc = wid % WC;
+  const int64_t ntm = np / BM;
+  const int64_t g = (ntm + 7) / 8;  // row tiles per XCD
+  const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+  const int64_t tm = xcd * g + idx % g, tn = idx / g;
+  if (tm >= ntm || tn >= ntn) return;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t zplane = np * np;
   const int KT = (int)(np / BK);
 
-  v4i acc[2][4][4];
+  v16i acc[CT][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int j = 0; j < CT; ++j)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int p = 0; p < 4; ++p) acc[i][j][p] = (v4i){0, 0, 0, 0};
+    for (int p = 0; p < 4; ++p) acc[j][p] = (v16i){};
 
-  v4i ra[4], rb[2];
+  v4i ra[A_LD], rb[B_LD];
   auto gload = [&](int kt) {
     const int64_t k0 = (int64_t)kt * BK;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)  // plane q, row tid/4, 16-byte chunk tid%4
-      ra[q] = *(const v4i*)(Zd + q * zplane + (m0 + (tid >> 2)) * np + k0 + 16 * (tid & 3));
+    for (int q = 0; q < A_LD; ++q) {  // chunk c: plane c / (4 BM), row (c / 4) % BM, 16 bytes c % 4
+      const int c = tid + NT * q;
+      ra[q] = *(const v4i*)(Zd + (c / (4 * BM)) * zplane + (m0 + (c >> 2) % BM) * np + k0 + 16 * (c & 3));
+    }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + 256 * q;
+    for (int q = 0; q < B_LD; ++q) {
+      const int c = tid + NT * q;
       rb[q] = *(const v4i*)(Gp + (n0 + (c >> 2)) * np + k0 + 16 * (c & 3));
     }
   };
@@ -81,10 +94,13 @@ __global__ void __launch_bounds__(256, (EPI == 1 && PL > 5) ? 1 : 2) k_rot_i8(in
     int8_t* As = smem + buf * A_STAGE;
     int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) *(v4i*)(As + (q * BM + (tid >> 2)) * LROW + 16 * (tid & 3)) = ra[q];
+    for (int q = 0; q < A_LD; ++q) {
+      const int c = tid + NT * q;
+      *(v4i*)(As + ((c / (4 * BM)) * BM + (c >> 2) % BM) * LROW + 16 * (c & 3)) = ra[q];
+    }
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int c = tid + 256 * q;
+    for (int q = 0; q < B_LD; ++q) {
+      const int c = tid + NT * q;
       *(v4i*)(Bs + (c >> 2) * LROW + 16 * (c & 3)) = rb[q];
     }
   };
@@ -97,18 +113,20 @@ __global__ void __launch_bounds__(256, (EPI == 1 && PL > 5) ? 1 : 2) k_rot_i8(in
     const int buf = kt & 1;
     const int8_t* As = smem + buf * A_STAGE;
     const int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
-    v4i b[4];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct)
-      b[ct] = *(const v4i*)(Bs + (64 * wc + 16 * ct + (lane & 15)) * LROW + 16 * (lane >> 4));
+    for (int ks = 0; ks < 2; ++ks) {
+      v4i b[CT], a[4];
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt)
+      for (int ct = 0; ct < CT; ++ct)
+        b[ct] = *(const v4i*)(Bs + (32 * (CT * wc + ct) + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const v4i a = *(const v4i*)(As + (p * BM + 32 * wr + 16 * rt + (lane & 15)) * LROW + 16 * (lane >> 4));
+      for (int p = 0; p < 4; ++p)
+        a[p] = *(const v4i*)(As + (p * BM + 32 * wr + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
 #pragma unroll
-        for (int ct = 0; ct < 4; ++ct) acc[rt][ct][p] = mfma_i8(a, b[ct], acc[rt][ct][p]);
-      }
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[p], b[ct], acc[ct][p]);
+    }
     if (kt + 1 < KT) {
       lstore(buf ^ 1);
       if (kt + 2 < KT) gload(kt + 2);
@@ -117,114 +135,91 @@ __global__ void __launch_bounds__(256, (EPI == 1 && PL > 5) ? 1 : 2) k_rot_i8(in
   }
 
   // epilogue tables in LDS (the staging buffers are free after the last barrier)
-  double* Qs = (double*)smem;              // [BM][PL]   (Z^T Q_L) rows of the tile
-  double* zS = Qs + BM * PL;               // [BM]       digit scales of Z^T rows
-  double* vS = zS + BM;                    // [BN][PL]   centring coefficients of the SNPs
-  double* Vs = vS + BN * PL;               // [BM][NP]   trait operand rows (EPI 1)
-  double* Ps = Vs + BM * NP;               // [2][BN][NP] row-half partial sums (EPI 1)
+  double* Qs = (double*)smem;   // [BM][PL]   (Z^T Q_L) rows of the tile
+  double* zS = Qs + BM * PL;    // [BM]       digit scales of Z^T rows
+  double* vS = zS + BM;         // [BN][PL]   centring coefficients of the SNPs
+  double* Vs = vS + BN * PL;    // [BM][NP]   trait operand rows (EPI 1)
+  double* Ps = Vs + BM * NP;    // [WR][BN][NP] per-wave-row partial sums (EPI 1)
+  static_assert((BM * (PL + 1 + NP) + BN * PL + WR * BN * NP) * 8 <= 2 * (A_STAGE + B_STAGE), "LDS reuse");
   const int64_t ss = snp_stride(PL);
-  for (int e = tid; e < BM * PL; e += 256) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
-  for (int e = tid; e < BM; e += 256) zS[e] = zs[m0 + e];
-  for (int e = tid; e < BN * PL; e += 256) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
+  for (int e = tid; e < BM * PL; e += NT) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
+  for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
+  for (int e = tid; e < BN * PL; e += NT) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
   if (EPI == 1)
-    for (int e = tid; e < BM * NP; e += 256) {
+    for (int e = tid; e < BM * NP; e += NT) {
       const int r = e / NP, q = e % NP;
       Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
     }
   __syncthreads();
 
-  // Row-outer epilogue over groups of CG columns: each of the lane's 8 rows
-  // reads its table entries once per group and serves the group's columns.
-  // The four digit-plane sums are first paired exactly in int32 (|sum| <
-  // 2^23 for n_pad <= 32768).
-  constexpr int CG = (EPI == 0) ? 4 : 1;
+  // one column tile at a time; the four digit-plane sums are first paired
+  // exactly in int32 (|sum| < 2^23 for n_pad <= 32768)
 #pragma unroll
-  for (int cg = 0; cg < 4; cg += CG) {
-    double vcol[CG][PL];
+  for (int ct = 0; ct < CT; ++ct) {
+    const int cl = 32 * (CT * wc + ct) + (lane & 31);
+    const int64_t col = n0 + cl;
+    double v[PL];
 #pragma unroll
-    for (int c = 0; c < CG; ++c)
+    for (int a = 0; a < PL; ++a) v[a] = vS[cl * PL + a];
+    double ps[NP];
+    double mx = 0.0;
 #pragma unroll
-      for (int a = 0; a < PL; ++a) vcol[c][a] = vS[(64 * wc + 16 * (cg + c) + (lane & 15)) * PL + a];
-    double ps[CG][NP];
-    double mx[CG];
+    for (int q = 0; q < NP; ++q) ps[q] = 0.0;
 #pragma unroll
-    for (int c = 0; c < CG; ++c) {
-      mx[c] = 0.0;
-#pragma unroll
-      for (int q = 0; q < NP; ++q) ps[c][q] = 0.0;
-    }
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-      const int rb0 = 32 * wr + 16 * rt + 4 * (lane >> 4);  // row within the tile
-      double xs[CG][4];
+    for (int gq = 0; gq < 4; ++gq) {
+      const int rb0 = 32 * wr + 8 * gq + 4 * (lane >> 5);  // row within the tile
+      double xs[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rr = rb0 + r;
-        const double z = zS[rr];
-        double qrow[PL];
+        const int rr = rb0 + r, e = 4 * gq + r;
+        const int hi = acc[ct][0][e] * 256 + acc[ct][1][e];
+        const int lo = acc[ct][2][e] * 256 + acc[ct][3][e];
+        double x = fma((double)hi, 65536.0, (double)lo) * zS[rr];
 #pragma unroll
-        for (int a = 0; a < PL; ++a) qrow[a] = Qs[rr * PL + a];
-        double vrow[NP];
-        if (EPI == 1) {
+        for (int a = 0; a < PL; ++a) x -= Qs[rr * PL + a] * v[a];
+        xs[r] = x;
+        if (EPI == 0) {
+          mx = fmax(mx, fabs(x));
+        } else {
 #pragma unroll
-          for (int q = 0; q < NP; ++q) vrow[q] = Vs[rr * NP + q];
-        }
-#pragma unroll
-        for (int c = 0; c < CG; ++c) {
-          const int ct = cg + c;
-          const int hi = acc[rt][ct][0][r] * 256 + acc[rt][ct][1][r];
-          const int lo = acc[rt][ct][2][r] * 256 + acc[rt][ct][3][r];
-          double x = fma((double)hi, 65536.0, (double)lo) * z;
-#pragma unroll
-          for (int a = 0; a < PL; ++a) x -= qrow[a] * vcol[c][a];
-          xs[c][r] = x;
-          if (EPI == 0) {
-            mx[c] = fmax(mx[c], fabs(x));
-          } else {
-#pragma unroll
-            for (int q = 0; q <= PL; ++q) ps[c][q] += vrow[q] * x;
-            ps[c][PL + 1] += vrow[PL + 1] * x * x;
-          }
+          for (int q = 0; q <= PL; ++q) ps[q] += Vs[rr * NP + q] * x;
+          ps[PL + 1] += Vs[rr * NP + PL + 1] * x * x;
         }
       }
-      if (EPI == 0) {
-#pragma unroll
-        for (int c = 0; c < CG; ++c) {
-          const int64_t col = n0 + 64 * wc + 16 * (cg + c) + (lane & 15);
-          *(v4d*)(X + col * np + m0 + rb0) = (v4d){xs[c][0], xs[c][1], xs[c][2], xs[c][3]};
-        }
-      }
+      if (EPI == 0) *(v4d*)(X + col * np + m0 + rb0) = (v4d){xs[0], xs[1], xs[2], xs[3]};
+      __builtin_amdgcn_sched_barrier(0);  // keep the row groups' table reads from being hoisted together
     }
+    if (EPI == 0) {
+      const double m = fmax(mx, __shfl_xor(mx, 32, 64));
+      if ((lane >> 5) == 0 && col < mb)
+        atomicMax((unsigned long long*)(sstat + col * ss + 2 * PL + 2), (unsigned long long)__double_as_longlong(m));
+    } else {
 #pragma unroll
-    for (int c = 0; c < CG; ++c) {
-      const int cl = 64 * wc + 16 * (cg + c) + (lane & 15);
-      const int64_t col = n0 + cl;
-      if (EPI == 0) {
-        double m = fmax(mx[c], __shfl_xor(mx[c], 16, 64));
-        m = fmax(m, __shfl_xor(m, 32, 64));
-        if ((lane >> 4) == 0 && col < mb)
-          atomicMax((unsigned long long*)(sstat + col * ss + 2 * PL + 2), (unsigned long long)__double_as_longlong(m));
-      } else {
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          double v = ps[c][q] + __shfl_xor(ps[c][q], 16, 64);
-          v += __shfl_xor(v, 32, 64);
-          if ((lane >> 4) == 0) Ps[(wr * BN + cl) * NP + q] = v;
-        }
+      for (int q = 0; q < NP; ++q) {
+        const double sq = ps[q] + __shfl_xor(ps[q], 32, 64);
+        if ((lane >> 5) == 0) Ps[(wr * BN + cl) * NP + q] = sq;
       }
     }
   }
   if (EPI == 1) {
     __syncthreads();
-    // the two row halves of the tile combine (fixed order); one partial per
+    // the WR row slices of the tile combine (fixed order); one partial per
     // (row tile, SNP)
-    const int64_t rtile = m0 / BM;
-    for (int e = tid; e < BN * NP; e += 256) {
+    for (int e = tid; e < BN * NP; e += NT) {
       const int cl = e % BN, q = e / BN;
-      part[(rtile * NP + q) * mbp + n0 + cl] = Ps[cl * NP + q] + Ps[(BN + cl) * NP + q];
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WR; ++w) sum += Ps[(w * BN + cl) * NP + q];
+      part[(tm * NP + q) * mbp + n0 + cl] = sum;
     }
   }
 }
+
+// Rotation tile configuration: CT 32-column MFMA tiles per wave, WR x WC waves.
+constexpr int ROT_CT = 2, ROT_WR = 2, ROT_WC = 2;
+constexpr int ROT_BM = 32 * ROT_WR;
+constexpr int ROT_BN = 32 * ROT_CT * ROT_WC;
+static_assert(SNP_PAD % ROT_BN == 0 && KPAD % ROT_BM == 0, "rotation tile must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
 // order and solves the cell (Schur complement, FP64).  A work-group takes 64
@@ -286,35 +281,34 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double*
 }
 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
-  const int64_t m_pad = roundup(m_blk, SNP_PAD);
   const Workspace& W = p.ws;
-  const int64_t ntn = m_pad / 128, ntiles = (p.n_pad / 64) * ntn;
-  dim3 grid((unsigned)(8 * ((ntiles + 7) / 8)));
-  if (p.fused_t1) {
-#define CLAK_R1(PLV)                                                                                              \
-  case PLV:                                                                                                       \
-    k_rot_i8<PLV, 1><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
-                                                 nullptr, W.V64, W.D64, W.part);                                  \
+  const int64_t ntn = roundup(m_blk, SNP_PAD) / ROT_BN, ntm = p.n_pad / ROT_BM;
+  dim3 grid((unsigned)(8 * ((ntm + 7) / 8) * ntn));
+  dim3 block(64 * ROT_WR * ROT_WC);
+#define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                    \
+  case PLV:                                                                                                   \
+    k_rot_i8<PLV, EPI, ROT_CT, ROT_WR, ROT_WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, \
+                                                                           W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, \
+                                                                           PP);                               \
     break;
+  if (p.fused_t1) {
     switch (p.pL) {
+#define CLAK_R1(PLV) CLAK_ROT(PLV, 1, nullptr, W.V64, W.D64, W.part)
       CLAK_R1(1) CLAK_R1(2) CLAK_R1(3) CLAK_R1(4) CLAK_R1(5) CLAK_R1(6) CLAK_R1(7) CLAK_R1(8)
+#undef CLAK_R1
       default:
         return hipErrorInvalidValue;
     }
-#undef CLAK_R1
     return hipGetLastError();
   }
-#define CLAK_R0(PLV)                                                                                              \
-  case PLV:                                                                                                       \
-    k_rot_i8<PLV, 0><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, \
-                                                 W.X64, nullptr, nullptr, nullptr);                               \
-    break;
   switch (p.pL) {
+#define CLAK_R0(PLV) CLAK_ROT(PLV, 0, W.X64, nullptr, nullptr, nullptr)
     CLAK_R0(1) CLAK_R0(2) CLAK_R0(3) CLAK_R0(4) CLAK_R0(5) CLAK_R0(6) CLAK_R0(7) CLAK_R0(8)
+#undef CLAK_R0
     default:
       return hipErrorInvalidValue;
   }
-#undef CLAK_R0
+#undef CLAK_ROT
   return hipGetLastError();
 }
 
@@ -440,9 +434,10 @@ hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, in
   const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;
   dim3 fgrid((unsigned)((m_blk + 63) / 64));
+  const int64_t nrt = p.prec == CLAK_PREC_MIXED ? p.n_pad / ROT_BM : p.n_pad / 64;
 #define CLAK_F1(PLV)                                                                                          \
   case PLV:                                                                                                   \
-    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(p.n_pad / 64, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, \
+    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags,          \
                                                d_b, d_se, f64, ldo, d_flags);                                 \
     break;
   switch (p.pL) {
