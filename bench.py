@@ -46,6 +46,9 @@ def parse():
                     help="call clak_run_block per block on one stream instead of the two-stream pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many bytes (reference for the "
+                         "rocprofv3 FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -113,8 +116,10 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager):
     The step time comes from HIP events around `steps` passes (pipeline
     launches unless eager).  The per-stage times come from the library's stage
     profiler, which brackets every stage's kernel with HIP events on the
-    stream it runs on; it needs eager launches, so it is measured over a
-    separate eager pass after the timed region."""
+    stream that kernel runs on; it is switched on for the timed region (its
+    events add a few microseconds between launches, so the step time is
+    taken from a first timed region without it and the stage times from a
+    second, profiled one of the same length)."""
     run = Pass(clak, plan, G, b, se, block, eager)
     try:
         for _ in range(warmup):
@@ -128,14 +133,40 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager):
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
+        clak.clak_plan_set_profiling(plan.handle, True)
+        for _ in range(steps):
+            run()
+        prof = clak.clak_plan_get_profile(plan.handle)
+        clak.clak_plan_set_profiling(plan.handle, False)
+        prof = {k: (v[0] / steps, v[1] / steps) for k, v in prof.items()}
     finally:
         run.close()
-    prof_pass = Pass(clak, plan, G, b, se, block, True)
-    clak.clak_plan_set_profiling(plan.handle, True)
-    prof_pass()
-    prof = clak.clak_plan_get_profile(plan.handle)
-    clak.clak_plan_set_profiling(plan.handle, False)
     return ms, prof
+
+
+KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): ("k_grid_i8", "k_mixed.hip"),
+           ("rotate", "fp64"): ("k_rot64", "k_fp64.hip"), ("grid", "fp64"): ("k_grid64", "k_fp64.hip")}
+
+
+def committed_traffic(stage, precision, workload):
+    """HBM bytes per launch of the stage's kernel from the committed rocprofv3
+    summaries (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when
+    none matches the current kernel source."""
+    import glob
+    import hashlib
+    key = KERNELS.get((stage, precision))
+    if key is None:
+        return None
+    kernel, src = key
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1207_2169_amd", "csrc", src), "rb").read()).hexdigest()[:16]
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for line in open(path):
+            if "traffic_bytes_per_launch=" not in line:
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
+            if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("sha256_16") == sha:
+                return float(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def stage_flops(stage, w, block):
@@ -198,6 +229,12 @@ def main():
     from paper_1207_2169_amd import clak
     from synth import make_workload
 
+    if args.copy_bytes:
+        src = torch.ones(args.copy_bytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cfg, wname = WORKLOADS[args.workload]
     kw = {} if args.m is None else {"m": args.m}
     log(f"[bench] generating workload {args.workload}: {wname}")
@@ -223,7 +260,8 @@ def main():
     if flops is not None:
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": dom, "avg_launch_ms": avg_ms, "launches": prof[dom][1],
+                "traffic": committed_traffic(dom, args.precision, args.workload), "kernel": KERNELS.get(
+                    (dom, args.precision), (dom,))[0], "avg_launch_ms": avg_ms, "launches_per_step": prof[dom][1],
                 "peak_source": peak_name}
         if args.precision == "mixed" and dom == "rotate":
             roof["issued_int8_ops_frac"] = 4 * achieved / peak  # four digit planes of Z^T per product

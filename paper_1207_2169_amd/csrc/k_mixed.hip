@@ -29,10 +29,13 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 // digit planes of Z^T for them (v_mfma_i32_32x32x32_i8), so one genotype
 // fragment feeds four MFMAs.  The K loop runs over 64-deep slices with LDS
 // double buffering (one barrier per slice; the next slice's global loads are
-// in flight during the current slice's MFMAs).  XCD x (work-groups are
-// dispatched round-robin over the 8 XCDs) owns a fixed slice of row tiles and
-// walks every SNP tile over it, so its slice of the Z^T digit planes stays in
-// that XCD's L2 while the genotype panel streams.
+// in flight during the current slice's MFMAs).  Work-groups are dispatched
+// round-robin over the 8 XCDs; the tiles are laid out as a 2 x 4 grid of (row
+// group, SNP group) so that XCD x owns half of the Z^T rows (which stay in its
+// L2) for a quarter of the SNP tiles, walking each SNP tile over its row tiles
+// before moving on (the genotype tile is then reused from L2).  Z^T is read
+// twice per block and the genotype panel four times, instead of eight times
+// one or the other.
 // Per element, the planes are recombined exactly, scaled, and the centring
 // term (Z^T Q_L)[k] . v(i) is subtracted (FP64).  Then
 //   EPI 0: the value is stored (SNP-major) and the SNP's max |x~_k| is raised
@@ -48,8 +51,10 @@ __device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
+constexpr int ROT_RG = 2, ROT_SG = 4;  // XCD grid: row groups x SNP groups
+
 template <int PL, int EPI, int CT, int WR, int WC>
-__global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5)) ? 1 : 2)
+__global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2)
     k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, const int8_t* __restrict__ Zd,
              const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
              double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
@@ -62,10 +67,10 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5))
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid / WC, wc = wid % WC;
   const int64_t ntm = np / BM;
-  const int64_t g = (ntm + 7) / 8;  // row tiles per XCD
+  const int64_t gm = (ntm + ROT_RG - 1) / ROT_RG, gn = (ntn + ROT_SG - 1) / ROT_SG;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-  const int64_t tm = xcd * g + idx % g, tn = idx / g;
-  if (tm >= ntm || tn >= ntn) return;
+  const int64_t tm = (xcd % ROT_RG) * gm + idx % gm, tn = (xcd / ROT_RG) * gn + idx / gm;
+  if (tm >= ntm || tn >= ntn || idx >= gm * gn) return;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t zplane = np * np;
   const int KT = (int)(np / BK);
@@ -134,6 +139,17 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5))
     __syncthreads();
   }
 
+  // pair the four digit-plane sums exactly in int32 (|sum| < 2^23 for
+  // n_pad <= 32768), halving the live accumulator registers
+  int hi[CT][16], lo[CT][16];
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      hi[ct][e] = acc[ct][0][e] * 256 + acc[ct][1][e];
+      lo[ct][e] = acc[ct][2][e] * 256 + acc[ct][3][e];
+    }
+
   // epilogue tables in LDS (the staging buffers are free after the last barrier)
   double* Qs = (double*)smem;   // [BM][PL]   (Z^T Q_L) rows of the tile
   double* zS = Qs + BM * PL;    // [BM]       digit scales of Z^T rows
@@ -152,8 +168,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5))
     }
   __syncthreads();
 
-  // one column tile at a time; the four digit-plane sums are first paired
-  // exactly in int32 (|sum| < 2^23 for n_pad <= 32768)
+  // one column tile at a time
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     const int cl = 32 * (CT * wc + ct) + (lane & 31);
@@ -172,9 +187,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 5))
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = rb0 + r, e = 4 * gq + r;
-        const int hi = acc[ct][0][e] * 256 + acc[ct][1][e];
-        const int lo = acc[ct][2][e] * 256 + acc[ct][3][e];
-        double x = fma((double)hi, 65536.0, (double)lo) * zS[rr];
+        double x = fma((double)hi[ct][e], 65536.0, (double)lo[ct][e]) * zS[rr];
 #pragma unroll
         for (int a = 0; a < PL; ++a) x -= Qs[rr * PL + a] * v[a];
         xs[r] = x;
@@ -283,7 +296,8 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double*
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   const Workspace& W = p.ws;
   const int64_t ntn = roundup(m_blk, SNP_PAD) / ROT_BN, ntm = p.n_pad / ROT_BM;
-  dim3 grid((unsigned)(8 * ((ntm + 7) / 8) * ntn));
+  const int64_t gm = (ntm + ROT_RG - 1) / ROT_RG, gn = (ntn + ROT_SG - 1) / ROT_SG;
+  dim3 grid((unsigned)(8 * gm * gn));
   dim3 block(64 * ROT_WR * ROT_WC);
 #define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                    \
   case PLV:                                                                                                   \
