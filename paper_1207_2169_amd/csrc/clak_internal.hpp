@@ -17,7 +17,7 @@ namespace clak {
 // every GEMM on the path) and of the SNP axis of a block.
 constexpr int64_t KPAD = 128;
 constexpr int64_t SNP_PAD = 256;  // multiple of every SNP tile width
-constexpr int64_t TRAIT_PAD = 16;
+constexpr int64_t TRAIT_PAD = 128;
 constexpr int MAX_PL = 16;
 constexpr int ING_MAX_SPLITS = 8;  // individual windows of the ingest are split over at most this many work-groups
 // int8 digit encoding: a value v with |v| <= s is stored as
@@ -90,9 +90,9 @@ struct Workspace {
   // mixed path
   int8_t* Zd = nullptr;     // 4 planes x n_pad x n_pad: digits of Z^T rows
   double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
-  int8_t* Xd = nullptr;     // 8 planes x mb_pad x n_pad: digits of x and x^2 (row = SNP)
-  int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) x n_pad
-  int8_t* Dd = nullptr;     // 4 planes x t_pad x n_pad
+  int8_t* Xd = nullptr;     // 8 planes x mb_pad rows (SNPs) x n_pad, K-tiled (kt32): digits of x, then x^2
+  int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) rows x n_pad, K-tiled (kt32)
+  int8_t* Dd = nullptr;     // 4 planes x t_pad rows x n_pad, K-tiled (kt32)
   double* vs = nullptr;     // t_pad*(pL+1) digit scales of the operand columns
   double* ds = nullptr;     // t_pad digit scales of d_j
 };

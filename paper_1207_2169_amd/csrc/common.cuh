@@ -66,6 +66,14 @@ __device__ __forceinline__ void digits4(int q, int8_t* d) {
   d[3] = (int8_t)l3;
 }
 
+// Offset of byte k of row `row` in a K-tiled digit plane of `rows` rows: the
+// n_pad bytes of each row are cut into 32-byte slices and slice s of every row
+// is stored contiguously (s * 32 rows + 32 row + k % 32), so one 32-deep stage
+// of a tile of consecutive rows is a single contiguous run.
+__host__ __device__ __forceinline__ int64_t kt32(int64_t row, int64_t k, int64_t rows) {
+  return (k >> 5) * rows * 32 + row * 32 + (k & 31);
+}
+
 // rint(v * inv_scale * QMAX) clamped to [-QMAX, QMAX].
 __device__ __forceinline__ int quantize(double v, double inv_scale) {
   double q = rint(v * inv_scale * QMAX);

@@ -266,14 +266,15 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
 }
 
 // Digit encoding of the rotated SNPs for the grid contraction: x with scale
-// max_k |x_k|, x o x with scale (max_k |x_k|)^2, four planes each, four
-// consecutive eigen rows per thread.
-__global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double* __restrict__ X,
-                                               const double* __restrict__ sstat, int8_t* __restrict__ Xd,
-                                               int64_t xplane) {
-  const int64_t i = blockIdx.y;
-  const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (k >= np) return;
+// max_k |x_k|, x o x with scale (max_k |x_k|)^2, four planes each, written
+// K-tiled.  A work-group takes one 32-deep slice of 32 SNPs; eight threads
+// share a SNP (four eigen rows each), so every plane receives one contiguous
+// kilobyte per work-group.
+__global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, const double* __restrict__ X,
+                                               const double* __restrict__ sstat, int8_t* __restrict__ Xd) {
+  const int64_t i = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
+  const int64_t k = (int64_t)blockIdx.y * 32 + 4 * (threadIdx.x & 7);
+  const int64_t xplane = mbp * np;
   const double mx = sstat[i * snp_stride(pL) + 2 * pL + 2];
   const double inv = mx > 0.0 ? 1.0 / mx : 0.0, inv2 = inv * inv;
   const v4d x = *(const v4d*)(X + i * np + k);
@@ -289,8 +290,9 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int pL, const double*
       pk[4 + q] |= ((int32_t)(uint8_t)e[q]) << (8 * r);
     }
   }
+  const int64_t off = kt32(i, k, mbp);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + i * np + k) = pk[q];
+  for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + off) = pk[q];
 }
 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
@@ -328,8 +330,8 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
 
 hipError_t launch_encode(const Plan& p, int64_t m_blk) {
   if (p.prec != CLAK_PREC_MIXED || p.fused_t1) return hipSuccess;
-  dim3 qgrid((unsigned)((p.n_pad / 4 + 255) / 256), (unsigned)roundup(m_blk, 64));
-  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, (int)p.pL, p.ws.X64, p.ws.sstat, p.ws.Xd, p.mb_pad * p.n_pad);
+  dim3 qgrid((unsigned)((m_blk + 31) / 32), (unsigned)(p.n_pad / 32));
+  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, p.mb_pad, (int)p.pL, p.ws.X64, p.ws.sstat, p.ws.Xd);
   return hipGetLastError();
 }
 // ------------------------------------------------------------------ grid
@@ -341,7 +343,8 @@ hipError_t launch_encode(const Plan& p, int64_t m_blk) {
 // 16 d columns.  Digit products are grouped by total weight g = a + b <= 3
 // into four exact int32 accumulators.
 template <int PL>
-__global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int64_t t, const int8_t* __restrict__ Xd,
+__global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int64_t mbp, int64_t t, int64_t tp,
+                                                 const int8_t* __restrict__ Xd,
                                                  int64_t xplane, const int8_t* __restrict__ Vd,
                                                  int64_t vplane, const int8_t* __restrict__ Dd, int64_t dplane,
                                                  const double* __restrict__ vs, const double* __restrict__ ds,
@@ -371,14 +374,14 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
     for (int q = 0; q < 8; ++q) {
       const int c = tid + 256 * q;
       const int pl = c >> 8, s = (c >> 2) & 63, kq = c & 3;
-      *(v4i*)(&As[pl][s][16 * kq]) = *(const v4i*)(Xd + pl * xplane + (i0 + s) * np + k0 + 16 * kq);
+      *(v4i*)(&As[pl][s][16 * kq]) = *(const v4i*)(Xd + pl * xplane + kt32(i0 + s, k0 + 16 * kq, mbp));
     }
     // B: 4 planes x NC columns x 64 bytes
     for (int c = tid; c < 4 * NC * 4; c += 256) {
       const int pl = c / (NC * 4), rem = c % (NC * 4), col = rem >> 2, kq = rem & 3;
-      const int8_t* src = (col < NCV) ? Vd + pl * vplane + (j0 * (PL + 1) + col) * np
-                                      : Dd + pl * dplane + (j0 + col - NCV) * np;
-      *(v4i*)(&Bs[pl][col][16 * kq]) = *(const v4i*)(src + k0 + 16 * kq);
+      const int8_t* src = (col < NCV) ? Vd + pl * vplane + kt32(j0 * (PL + 1) + col, k0 + 16 * kq, tp * (PL + 1))
+                                      : Dd + pl * dplane + kt32(j0 + col - NCV, k0 + 16 * kq, tp);
+      *(v4i*)(&Bs[pl][col][16 * kq]) = *(const v4i*)src;
     }
     __syncthreads();
     v4i xa[4], xq[4];
@@ -443,6 +446,172 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
   }
 }
 
+// Grid contraction on v_mfma_i32_32x32x32_i8 for p_L <= 3.  A work-group
+// takes 128 SNPs (one 32-SNP row tile per wave) x TT traits and keeps at most
+// four 32 x 32 output tiles per wave (four digit-weight accumulators each,
+// 256 accumulation registers).  It runs 1 + TT / 32 passes over K:
+//   pass 0     : a = d^T (x o x) for the TT traits (x o x digits against d),
+//                parked in FP64 registers;
+//   pass 1 + g : for trait group g (32 traits), the p_L + 1 operand entries
+//                q (q < p_L whitened covariates, q = p_L weighted residual)
+//                against x, one 32-column tile per entry; then each lane
+//                holds complete cells (16 SNPs of one trait) and solves them.
+// The operand columns of a trait group are regrouped by entry while staging,
+// so each MFMA tile is one entry of 32 traits.  All passes form one sequence
+// of 32-deep stages, double-buffered in LDS with a 48-byte row pitch
+// (conflict-free 16-byte fragment reads), so the loads of the next pass are
+// in flight during a pass's epilogue.  With the K-tiled digit layout every
+// stage of a row tile is one contiguous run in HBM.  Work-groups go
+// round-robin over the 8 XCDs; XCD x owns trait group x % xt (of xt groups)
+// and SNP group x / xt, so its share of the trait operand stays in its L2.
+constexpr int G32_PITCH = 48, G32_BM = 128, G32_STAGE = (4 * G32_BM + 4 * 4 * 32) * G32_PITCH;
+
+// One 32-deep stage: NT output tiles of 32 x 32, digit products grouped by
+// weight a + b <= 3 into acc[t][a + b].
+template <int NT>
+__device__ __forceinline__ void g32_stage(v16i (&acc)[4][4], const int8_t* As, const int8_t* Bs, int afrag,
+                                          int bfrag) {
+  v4i a[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) a[p] = *(const v4i*)(As + p * G32_BM * G32_PITCH + afrag);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    v4i b[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(Bs + (p * 4 + t) * 32 * G32_PITCH + bfrag);
+    acc[t][0] = mfma32_i8(a[0], b[0], acc[t][0]);
+    acc[t][1] = mfma32_i8(a[0], b[1], acc[t][1]);
+    acc[t][2] = mfma32_i8(a[0], b[2], acc[t][2]);
+    acc[t][3] = mfma32_i8(a[0], b[3], acc[t][3]);
+    acc[t][1] = mfma32_i8(a[1], b[0], acc[t][1]);
+    acc[t][2] = mfma32_i8(a[1], b[1], acc[t][2]);
+    acc[t][3] = mfma32_i8(a[1], b[2], acc[t][3]);
+    acc[t][2] = mfma32_i8(a[2], b[0], acc[t][2]);
+    acc[t][3] = mfma32_i8(a[2], b[1], acc[t][3]);
+    acc[t][3] = mfma32_i8(a[3], b[0], acc[t][3]);
+  }
+}
+
+__device__ __forceinline__ double g32_value(const v16i (&acc)[4], int r) {
+  return (((double)acc[0][r] * 256.0 + (double)acc[1][r]) * 256.0 + (double)acc[2][r]) * 256.0 + (double)acc[3][r];
+}
+
+// One pass over K into NT accumulator tiles.  pa: this thread's 16-byte chunk
+// of digit plane 0 of the SNP row tile (planes xplane apart, stages astride
+// apart); pb: its chunk of the first 32 operand rows (further 32-row groups
+// 1024 bytes apart, stages bstride apart).  REGROUP reorders the staged
+// operand rows from (trait, entry) to (entry, trait) order, NV entries a trait.
+template <int NT, bool REGROUP, int NV>
+__device__ __forceinline__ void g32_pass(v16i (&acc)[4][4], int8_t* smem, const int8_t* pa, int64_t xplane,
+                                         int64_t astride, const int8_t* pb, int64_t bstride, int KT, int afrag,
+                                         int bfrag) {
+  const int tid = threadIdx.x, half = tid & 1, bpl = tid >> 6, brow = (tid & 63) >> 1;
+  v4i ra[4], rb[NT];
+  auto gload = [&](int kt) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) ra[p] = *(const v4i*)(pa + p * xplane + kt * astride);
+#pragma unroll
+    for (int u = 0; u < NT; ++u) rb[u] = *(const v4i*)(pb + u * 1024 + kt * bstride);
+  };
+  auto lstore = [&](int buf) {
+    int8_t* As = smem + buf * G32_STAGE;
+    int8_t* Bs = As + 4 * G32_BM * G32_PITCH;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) *(v4i*)(As + (p * G32_BM + (tid >> 1)) * G32_PITCH + 16 * half) = ra[p];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) {
+      const int c = 32 * u + brow;
+      const int lrow = REGROUP ? (c % NV) * 32 + c / NV : c;
+      *(v4i*)(Bs + (bpl * 4 * 32 + lrow) * G32_PITCH + 16 * half) = rb[u];
+    }
+  };
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  if (KT > 1) gload(1);
+  for (int kt = 0; kt < KT; ++kt) {
+    const int8_t* As = smem + (kt & 1) * G32_STAGE;
+    g32_stage<NT>(acc, As, As + 4 * G32_BM * G32_PITCH, afrag, bfrag);
+    if (kt + 1 < KT) {
+      lstore((kt + 1) & 1);
+      if (kt + 2 < KT) gload(kt + 2);
+    }
+    __syncthreads();
+  }
+}
+
+template <int PL, int TT>
+__global__ void __launch_bounds__(256, 1)
+    k_grid32(int64_t np, int64_t m_blk, int64_t mbp, int64_t t, int64_t tp, int64_t ntn, int64_t ntt, int xt,
+             const int8_t* __restrict__ Xd, const int8_t* __restrict__ Vd, const int8_t* __restrict__ Dd,
+             const double* __restrict__ vs, const double* __restrict__ ds, const double* __restrict__ tpar,
+             const double* __restrict__ sstat, uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
+             int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
+  constexpr int NV = PL + 1, NG = TT / 32;
+  static_assert(NV <= 4 && NG <= 4, "at most four accumulator tiles per wave");
+  __shared__ __attribute__((aligned(16))) int8_t smem[2 * G32_STAGE];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, half = tid & 1;
+  const int bpl = tid >> 6, brow = (tid & 63) >> 1;
+  const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8, xs = 8 / xt;
+  const int64_t gt = (ntt + xt - 1) / xt, gs = (ntn + xs - 1) / xs;
+  const int64_t tt = (xcd % xt) * gt + idx % gt, tn = (xcd / xt) * gs + idx / gt;
+  if (idx >= gt * gs || tt >= ntt || tn >= ntn) return;
+  const int64_t i0 = tn * G32_BM, j0 = tt * TT;
+  const int64_t xplane = mbp * np, vrows = tp * NV, vplane = vrows * np, dplane = tp * np;
+  const int KT = (int)(np / 32);
+  const int afrag = (32 * wid + (lane & 31)) * G32_PITCH + 16 * (lane >> 5);
+  const int bfrag = (lane & 31) * G32_PITCH + 16 * (lane >> 5);
+  const int8_t* pa = Xd + i0 * 32 + 16 * tid;
+  const int64_t ss = snp_stride(PL);
+
+  v16i acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[u][g] = (v16i){};
+  // pass 0: a = d^T (x o x) of the TT traits, unscaled
+  g32_pass<NG, false, NV>(acc, smem, pa + 4 * xplane, xplane, mbp * 32,
+                          Dd + bpl * dplane + (j0 + brow) * 32 + 16 * half, tp * 32, KT, afrag, bfrag);
+  double araw[NG][16];
+#pragma unroll
+  for (int u = 0; u < NG; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) araw[u][r] = g32_value(acc[u], r);
+
+#pragma unroll
+  for (int g = 0; g < NG; ++g) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[u][e] = (v16i){};
+    g32_pass<NV, true, NV>(acc, smem, pa, xplane, mbp * 32,
+                           Vd + bpl * vplane + ((j0 + 32 * g) * NV + brow) * 32 + 16 * half, vrows * 32, KT, afrag,
+                           bfrag);
+    // lane: trait j0 + 32 g + lane % 32, SNP rows 8 (r / 4) + 4 (lane / 32) + r % 4 of the wave's tile
+    const int64_t j = j0 + 32 * g + (lane & 31);
+    if (j < t) {
+      double sc[NV];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) sc[q] = vs[j * NV + q] * (1.0 / 127.0);
+      const double sd = ds[j] * (1.0 / 127.0);
+      const double* tpj = tpar + j * trait_stride(PL);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t i = i0 + 32 * wid + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (i < m_blk) {
+          const double* st = sstat + i * ss;
+          const double gx = st[2 * PL + 2];  // max_k |x~_k| of SNP i
+          double v[NV];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) v[q] = g32_value(acc[q], r) * sc[q] * gx;
+          schur_store<PL>(v, v[PL], araw[g][r] * sd * gx * gx, tpj, st, flags, i, j, ob, ose, out_f64, ldo, oflags);
+        }
+        __builtin_amdgcn_sched_barrier(0);  // one cell at a time: keeps the accumulator reads from being hoisted
+      }
+    }
+  }
+}
+
 hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                          uint8_t* d_flags) {
   const int f64 = out_dtype == CLAK_OUT_F64;
@@ -469,15 +638,50 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
   const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;
   if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
+  if (p.pL <= 3) {
+    // traits per work-group: 64 unless 32 gives fewer modelled
+    // dispatch rounds of 256 work-groups x traits per tile
+    const int64_t ntn = (m_blk + G32_BM - 1) / G32_BM;
+    int tt = 32;
+    for (int c = 64; c <= 64; c *= 2) {
+      const int64_t r_c = (ntn * ((p.t + c - 1) / c) + 255) / 256, r_t = (ntn * ((p.t + tt - 1) / tt) + 255) / 256;
+      if (r_c * c <= r_t * tt) tt = c;
+    }
+    const int64_t ntt = (p.t + tt - 1) / tt;
+    int xt = 1;
+    while (xt < 8 && 2 * xt <= ntt) xt *= 2;
+    const int64_t gt = (ntt + xt - 1) / xt, gs = (ntn + 8 / xt - 1) / (8 / xt);
+    const dim3 g32((unsigned)(8 * gt * gs));
+#define CLAK_G32(PLV, TTV)                                                                                       \
+  k_grid32<PLV, TTV><<<g32, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, p.t, p.t_pad, ntn, ntt, xt, W.Xd, W.Vd, \
+                                                W.Dd, W.vs, W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, ldo,  \
+                                                d_flags)
+#define CLAK_G32T(PLV)   \
+  case PLV:              \
+    if (tt == 32)        \
+      CLAK_G32(PLV, 32); \
+    else                 \
+      CLAK_G32(PLV, 64); \
+    break;
+    switch (p.pL) {
+      CLAK_G32T(1) CLAK_G32T(2) CLAK_G32T(3)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef CLAK_G32T
+#undef CLAK_G32
+    return hipGetLastError();
+  }
   dim3 grid((unsigned)((m_blk + 63) / 64), (unsigned)(p.t_pad / 16));
   const int64_t xplane = p.mb_pad * p.n_pad, vplane = p.t_pad * (p.pL + 1) * p.n_pad, dplane = p.t_pad * p.n_pad;
 #define CLAK_GI8(PLV)                                                                                              \
   case PLV:                                                                                                        \
-    k_grid_i8<PLV><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.t, W.Xd, xplane, W.Vd, vplane, W.Dd, dplane, W.vs, \
-                                               W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, ldo, d_flags);      \
+    k_grid_i8<PLV><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, p.t, p.t_pad, W.Xd, xplane, W.Vd, vplane, \
+                                               W.Dd, dplane, W.vs, W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, \
+                                               ldo, d_flags);                                                      \
     break;
   switch (p.pL) {
-    CLAK_GI8(1) CLAK_GI8(2) CLAK_GI8(3) CLAK_GI8(4) CLAK_GI8(5) CLAK_GI8(6) CLAK_GI8(7) CLAK_GI8(8)
+    CLAK_GI8(4) CLAK_GI8(5) CLAK_GI8(6) CLAK_GI8(7) CLAK_GI8(8)
     default:
       return hipErrorInvalidValue;
   }

@@ -172,11 +172,11 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
     for (int64_t k = threadIdx.x; k < np; k += blockDim.x) {
       for (int l = 0; l < ncol; ++l) {
         if (Vd)
-          for (int q = 0; q < 4; ++q) Vd[q * vplane + (j * ncol + l) * np + k] = 0;
+          for (int q = 0; q < 4; ++q) Vd[q * vplane + kt32(j * ncol + l, k, tp * ncol)] = 0;
         if (V64) V64[(j * ncol + l) * np + k] = 0.0;
       }
       if (Dd)
-        for (int q = 0; q < 4; ++q) Dd[q * dplane + j * np + k] = 0;
+        for (int q = 0; q < 4; ++q) Dd[q * dplane + kt32(j, k, tp)] = 0;
       if (D64) D64[j * np + k] = 0.0;
     }
     if (threadIdx.x == 0) {
@@ -356,9 +356,9 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
         digits4(quantize(v[l], inv), d);
         for (int q = 0; q < 4; ++q) {
           if (l < ncol)
-            Vd[q * vplane + (j * ncol + l) * np + k] = d[q];
+            Vd[q * vplane + kt32(j * ncol + l, k, tp * ncol)] = d[q];
           else
-            Dd[q * dplane + j * np + k] = d[q];
+            Dd[q * dplane + kt32(j, k, tp)] = d[q];
         }
       }
     }

@@ -41,6 +41,32 @@ def test_mixed_vs_oracle(cfg, kw, block):
     assert eb < TOL and es < TOL
 
 
+def test_mixed_wide_trait_tiles_sampled():
+    """m = 2048 SNPs x t = 1000 traits in one block: 16 SNP tiles x 16 tiles of
+    64 traits fill exactly one dispatch round, so the grid kernel takes its
+    64-trait tile (two trait groups per work-group).  Every cell must be
+    finite and unflagged; 30000 sampled cells, plus all cells of the traits
+    and SNPs at tile edges and the ragged trait tail, match the oracle."""
+    from paper_1207_2169_amd import clak
+    w = make_workload(2, n=256, m=2048, t=1000, kin_cols=512)
+    print(f"mixed wide tiles n={w.n} m={w.m} t={w.t}", flush=True)
+    b, se, fl = gpu_run(w, clak.CLAK_PREC_MIXED, block=2048, out_dtype="f64")
+    assert (fl == 0).all() and np.isfinite(b).all() and np.isfinite(se).all()
+    rng = np.random.default_rng(7)
+    ii = rng.integers(0, w.m, 30000)
+    jj = rng.integers(0, w.t, 30000)
+    edge_t = np.array([0, 31, 32, 63, 64, 127, 128, 959, 960, 991, 992, 999])
+    edge_s = np.array([0, 31, 32, 127, 128, 1023, 1024, 2047])
+    e1 = np.meshgrid(np.arange(0, w.m, 37), edge_t, indexing="ij")
+    e2 = np.meshgrid(edge_s, np.arange(w.t), indexing="ij")
+    ii = np.concatenate([ii, e1[0].ravel(), e2[0].ravel()])
+    jj = np.concatenate([jj, e1[1].ravel(), e2[1].ravel()])
+    rb, rse, rfl = oracle_cells(w, ii, jj)
+    eb, es = errors(b[ii, jj], se[ii, jj], rb[:, -1], rse)
+    print(f"eps_b={eb:.3e} eps_se={es:.3e} cells={ii.size}")
+    assert eb < TOL and es < TOL
+
+
 def test_mixed_full_vector_and_paper_variance():
     from paper_1207_2169_amd import clak
     w = make_workload(2, n=200, m=70, t=5, kin_cols=400)
