@@ -78,7 +78,7 @@ struct Workspace {
   double* Yt = nullptr;     // n_pad x t  column-major: Z^T Y
   double* tpar = nullptr;   // t_pad x trait_stride
   // per block (the slot selected for the block being launched)
-  int8_t* Gp = nullptr;     // mb_pad x n_pad: SNP rows, individuals contiguous, zero padded
+  int8_t* Gp = nullptr;     // mb_pad SNP rows x n_pad individuals, K-tiled (kt32), zero padded
   double* sstat = nullptr;  // mb_pad x snp_stride
   double* ipart = nullptr;  // ingest partials: [ING_MAX_SPLITS][pL+2][mb_pad]
   // rotated, centred SNPs in FP64 (both paths)
@@ -88,10 +88,10 @@ struct Workspace {
   double* D64 = nullptr;    // t_pad x n_pad: d_j
   double* part = nullptr;   // fused t = 1 kernel: [n_pad/64][pL+2][mb_pad] partial sums
   // mixed path
-  int8_t* Zd = nullptr;     // 4 planes x n_pad x n_pad: digits of Z^T rows
+  int8_t* Zd = nullptr;     // 4 planes x n_pad rows (Z^T) x n_pad, K-tiled (kt32)
   double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
   int8_t* Xd = nullptr;     // 8 planes x mb_pad rows (SNPs) x n_pad, K-tiled (kt32): digits of x, then x^2
-  int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) rows x n_pad, K-tiled (kt32)
+  int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) rows (vrow order) x n_pad, K-tiled (kt32)
   int8_t* Dd = nullptr;     // 4 planes x t_pad rows x n_pad, K-tiled (kt32)
   double* vs = nullptr;     // t_pad*(pL+1) digit scales of the operand columns
   double* ds = nullptr;     // t_pad digit scales of d_j

@@ -74,6 +74,13 @@ __host__ __device__ __forceinline__ int64_t kt32(int64_t row, int64_t k, int64_t
   return (k >> 5) * rows * 32 + row * 32 + (k & 31);
 }
 
+// Row of operand entry q of trait j in the per-trait operand planes: traits
+// are grouped by 32 and, within a group, stored entry by entry, so the 32
+// traits of a group have each entry in 32 consecutive rows.
+__host__ __device__ __forceinline__ int64_t vrow(int64_t j, int64_t q, int64_t nent) {
+  return (j >> 5) * 32 * nent + q * 32 + (j & 31);
+}
+
 // rint(v * inv_scale * QMAX) clamped to [-QMAX, QMAX].
 __device__ __forceinline__ int quantize(double v, double inv_scale) {
   double q = rint(v * inv_scale * QMAX);

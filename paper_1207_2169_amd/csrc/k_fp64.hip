@@ -12,7 +12,7 @@ namespace clak {
 // C = Z^T B over the padded eigen index, 64 x 64 tiles, BK = 16.
 //   MODE 0: B real FP64, column-major (ldb), rows >= n and columns >= ncols
 //           read as zero; out[k + col * ldo] = C[k][col] for col < ncols.
-//   MODE 1: B = int8 SNP panel Gp (row = SNP, ld np); the centring
+//   MODE 1: B = int8 SNP panel Gp (ldb SNP rows, K-tiled); the centring
 //           x = C[k][col] - sum_a (Z^T Q_L)[k][a] v_a(col) is fused and the
 //           result stored SNP-major: out[col * np + k].
 //   MODE 2: as MODE 1, but with a single trait the cell sums of the tile's
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(256) k_rot64(int64_t n, int64_t np, int pL, co
       }
     } else {
       const int8_t* Gp = (const int8_t*)B;
-      const int32_t packed = *(const int32_t*)(Gp + (n0 + lr) * np + k0 + lk);
+      const int32_t packed = *(const int32_t*)(Gp + kt32(n0 + lr, k0 + lk, ldb));  // ldb: rows of the panel
 #pragma unroll
       for (int q = 0; q < 4; ++q) Bs[lk + q][lr] = (double)(int8_t)(packed >> (8 * q));
     }
@@ -147,10 +147,10 @@ hipError_t launch_rotate_snps_fp64(const Plan& p, int64_t m_blk) {
   dim3 grid((unsigned)(p.n_pad / 64), (unsigned)(m_pad / 64));
   const Workspace& W = p.ws;
   if (p.fused_t1)
-    k_rot64<2><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.n_pad, m_pad, nullptr, 0, W.Qt,
+    k_rot64<2><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.mb_pad, m_pad, nullptr, 0, W.Qt,
                                            W.sstat, W.V64, W.D64, W.part, p.mb_pad);
   else
-    k_rot64<1><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.n_pad, m_pad, W.X64, p.n_pad,
+    k_rot64<1><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.mb_pad, m_pad, W.X64, p.n_pad,
                                            W.Qt, W.sstat, nullptr, nullptr, nullptr, 0);
   return hipGetLastError();
 }

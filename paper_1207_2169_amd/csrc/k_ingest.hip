@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
       gd[e] = (double)by[e];
       gg += gd[e] * gd[e];
     }
-    if (snp < m_pad) __builtin_memcpy(__builtin_assume_aligned(Gp + snp * np + i0, 16), by, 16);
+    if (snp < m_pad) __builtin_memcpy(__builtin_assume_aligned(Gp + kt32(snp, i0, mbp), 16), by, 16);
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < PL; ++a) {

@@ -81,18 +81,25 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
 #pragma unroll
     for (int p = 0; p < 4; ++p) acc[j][p] = (v16i){};
 
+  // Staging: the 16-byte chunks of a stage go in groups of 64, one group per
+  // (plane, 32-row block, half of the 64-byte slice); lane l of a group takes
+  // row l % 32, chunk l / 32 of that half, the lane pattern of the fragment
+  // reads, so the LDS stores are free of bank conflicts.
   v4i ra[A_LD], rb[B_LD];
+  const int srow = lane & 31, sch = lane >> 5;
   auto gload = [&](int kt) {
     const int64_t k0 = (int64_t)kt * BK;
 #pragma unroll
-    for (int q = 0; q < A_LD; ++q) {  // chunk c: plane c / (4 BM), row (c / 4) % BM, 16 bytes c % 4
-      const int c = tid + NT * q;
-      ra[q] = *(const v4i*)(Zd + (c / (4 * BM)) * zplane + (m0 + (c >> 2) % BM) * np + k0 + 16 * (c & 3));
+    for (int q = 0; q < A_LD; ++q) {  // group (tid + NT q) / 64: half g % 2, row block (g / 2) % (BM / 32), plane
+      const int g = (tid + NT * q) >> 6;
+      const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
+      ra[q] = *(const v4i*)(Zd + pl * zplane + kt32(m0 + 32 * rb32 + srow, k0 + 32 * kh, np) + 16 * sch);
     }
 #pragma unroll
     for (int q = 0; q < B_LD; ++q) {
-      const int c = tid + NT * q;
-      rb[q] = *(const v4i*)(Gp + (n0 + (c >> 2)) * np + k0 + 16 * (c & 3));
+      const int g = (tid + NT * q) >> 6;
+      const int kh = g & 1, rb32 = g >> 1;
+      rb[q] = *(const v4i*)(Gp + kt32(n0 + 32 * rb32 + srow, k0 + 32 * kh, mbp) + 16 * sch);
     }
   };
   auto lstore = [&](int buf) {
@@ -100,13 +107,15 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
     int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
 #pragma unroll
     for (int q = 0; q < A_LD; ++q) {
-      const int c = tid + NT * q;
-      *(v4i*)(As + ((c / (4 * BM)) * BM + (c >> 2) % BM) * LROW + 16 * (c & 3)) = ra[q];
+      const int g = (tid + NT * q) >> 6;
+      const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
+      *(v4i*)(As + (pl * BM + 32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = ra[q];
     }
 #pragma unroll
     for (int q = 0; q < B_LD; ++q) {
-      const int c = tid + NT * q;
-      *(v4i*)(Bs + (c >> 2) * LROW + 16 * (c & 3)) = rb[q];
+      const int g = (tid + NT * q) >> 6;
+      const int kh = g & 1, rb32 = g >> 1;
+      *(v4i*)(Bs + (32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = rb[q];
     }
   };
 
@@ -379,8 +388,9 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
     // B: 4 planes x NC columns x 64 bytes
     for (int c = tid; c < 4 * NC * 4; c += 256) {
       const int pl = c / (NC * 4), rem = c % (NC * 4), col = rem >> 2, kq = rem & 3;
-      const int8_t* src = (col < NCV) ? Vd + pl * vplane + kt32(j0 * (PL + 1) + col, k0 + 16 * kq, tp * (PL + 1))
-                                      : Dd + pl * dplane + kt32(j0 + col - NCV, k0 + 16 * kq, tp);
+      const int8_t* src =
+          (col < NCV) ? Vd + pl * vplane + kt32(vrow(j0 + col / (PL + 1), col % (PL + 1), PL + 1), k0 + 16 * kq, tp * (PL + 1))
+                      : Dd + pl * dplane + kt32(j0 + col - NCV, k0 + 16 * kq, tp);
       *(v4i*)(&Bs[pl][col][16 * kq]) = *(const v4i*)src;
     }
     __syncthreads();
@@ -456,8 +466,8 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
 //                q (q < p_L whitened covariates, q = p_L weighted residual)
 //                against x, one 32-column tile per entry; then each lane
 //                holds complete cells (16 SNPs of one trait) and solves them.
-// The operand columns of a trait group are regrouped by entry while staging,
-// so each MFMA tile is one entry of 32 traits.  All passes form one sequence
+// The operand planes keep each entry of a 32-trait group in 32 consecutive
+// rows, so each MFMA tile is one entry of 32 traits.  All passes form one sequence
 // of 32-deep stages, double-buffered in LDS with a 48-byte row pitch
 // (conflict-free 16-byte fragment reads), so the loads of the next pass are
 // in flight during a pass's epilogue.  With the K-tiled digit layout every
@@ -496,16 +506,17 @@ __device__ __forceinline__ double g32_value(const v16i (&acc)[4], int r) {
   return (((double)acc[0][r] * 256.0 + (double)acc[1][r]) * 256.0 + (double)acc[2][r]) * 256.0 + (double)acc[3][r];
 }
 
-// One pass over K into NT accumulator tiles.  pa: this thread's 16-byte chunk
-// of digit plane 0 of the SNP row tile (planes xplane apart, stages astride
-// apart); pb: its chunk of the first 32 operand rows (further 32-row groups
-// 1024 bytes apart, stages bstride apart).  REGROUP reorders the staged
-// operand rows from (trait, entry) to (entry, trait) order, NV entries a trait.
-template <int NT, bool REGROUP, int NV>
+// One pass over K into NT accumulator tiles.  Lane l of wave w stages row
+// 32 w + l % 32, half l / 32, of each 32-row group: the same lane pattern as
+// the fragment reads, which keeps the LDS stores free of bank conflicts.
+// pa: this lane's chunk of digit plane 0 of the SNP row tile (planes xplane
+// apart, stages astride apart); pb: its chunk of operand plane w, first
+// 32-row group (further groups 1024 bytes apart, stages bstride apart).
+template <int NT>
 __device__ __forceinline__ void g32_pass(v16i (&acc)[4][4], int8_t* smem, const int8_t* pa, int64_t xplane,
                                          int64_t astride, const int8_t* pb, int64_t bstride, int KT, int afrag,
                                          int bfrag) {
-  const int tid = threadIdx.x, half = tid & 1, bpl = tid >> 6, brow = (tid & 63) >> 1;
+  const int wid = threadIdx.x >> 6;
   v4i ra[4], rb[NT];
   auto gload = [&](int kt) {
 #pragma unroll
@@ -517,13 +528,9 @@ __device__ __forceinline__ void g32_pass(v16i (&acc)[4][4], int8_t* smem, const 
     int8_t* As = smem + buf * G32_STAGE;
     int8_t* Bs = As + 4 * G32_BM * G32_PITCH;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) *(v4i*)(As + (p * G32_BM + (tid >> 1)) * G32_PITCH + 16 * half) = ra[p];
+    for (int p = 0; p < 4; ++p) *(v4i*)(As + p * G32_BM * G32_PITCH + afrag) = ra[p];
 #pragma unroll
-    for (int u = 0; u < NT; ++u) {
-      const int c = 32 * u + brow;
-      const int lrow = REGROUP ? (c % NV) * 32 + c / NV : c;
-      *(v4i*)(Bs + (bpl * 4 * 32 + lrow) * G32_PITCH + 16 * half) = rb[u];
-    }
+    for (int u = 0; u < NT; ++u) *(v4i*)(Bs + (wid * 4 + u) * 32 * G32_PITCH + bfrag) = rb[u];
   };
   gload(0);
   lstore(0);
@@ -550,8 +557,7 @@ __global__ void __launch_bounds__(256, 1)
   constexpr int NV = PL + 1, NG = TT / 32;
   static_assert(NV <= 4 && NG <= 4, "at most four accumulator tiles per wave");
   __shared__ __attribute__((aligned(16))) int8_t smem[2 * G32_STAGE];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6, half = tid & 1;
-  const int bpl = tid >> 6, brow = (tid & 63) >> 1;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8, xs = 8 / xt;
   const int64_t gt = (ntt + xt - 1) / xt, gs = (ntn + xs - 1) / xs;
   const int64_t tt = (xcd % xt) * gt + idx % gt, tn = (xcd / xt) * gs + idx / gt;
@@ -561,7 +567,9 @@ __global__ void __launch_bounds__(256, 1)
   const int KT = (int)(np / 32);
   const int afrag = (32 * wid + (lane & 31)) * G32_PITCH + 16 * (lane >> 5);
   const int bfrag = (lane & 31) * G32_PITCH + 16 * (lane >> 5);
-  const int8_t* pa = Xd + i0 * 32 + 16 * tid;
+  // this lane's staging chunk: row lane % 32 of a 32-row group, half lane / 32
+  const int lchunk = (lane & 31) * 32 + 16 * (lane >> 5);
+  const int8_t* pa = Xd + (i0 + 32 * wid) * 32 + lchunk;
   const int64_t ss = snp_stride(PL);
 
   v16i acc[4][4];
@@ -570,8 +578,8 @@ __global__ void __launch_bounds__(256, 1)
 #pragma unroll
     for (int g = 0; g < 4; ++g) acc[u][g] = (v16i){};
   // pass 0: a = d^T (x o x) of the TT traits, unscaled
-  g32_pass<NG, false, NV>(acc, smem, pa + 4 * xplane, xplane, mbp * 32,
-                          Dd + bpl * dplane + (j0 + brow) * 32 + 16 * half, tp * 32, KT, afrag, bfrag);
+  g32_pass<NG>(acc, smem, pa + 4 * xplane, xplane, mbp * 32, Dd + wid * dplane + j0 * 32 + lchunk, tp * 32, KT, afrag,
+               bfrag);
   double araw[NG][16];
 #pragma unroll
   for (int u = 0; u < NG; ++u)
@@ -584,9 +592,8 @@ __global__ void __launch_bounds__(256, 1)
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[u][e] = (v16i){};
-    g32_pass<NV, true, NV>(acc, smem, pa, xplane, mbp * 32,
-                           Vd + bpl * vplane + ((j0 + 32 * g) * NV + brow) * 32 + 16 * half, vrows * 32, KT, afrag,
-                           bfrag);
+    g32_pass<NV>(acc, smem, pa, xplane, mbp * 32, Vd + wid * vplane + vrow(j0 + 32 * g, 0, NV) * 32 + lchunk,
+                 vrows * 32, KT, afrag, bfrag);
     // lane: trait j0 + 32 g + lane % 32, SNP rows 8 (r / 4) + 4 (lane / 32) + r % 4 of the wave's tile
     const int64_t j = j0 + 32 * g + (lane & 31);
     if (j < t) {

@@ -42,7 +42,7 @@ __global__ void k_split_digits(int64_t n, int64_t np, const double* __restrict__
     int8_t d[4] = {0, 0, 0, 0};
     if (k < n && i < n) digits4(quantize(row[i], inv), d);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Zd[q * plane + k * np + i] = d[q];
+    for (int q = 0; q < 4; ++q) Zd[q * plane + kt32(k, i, np)] = d[q];
   }
   if (threadIdx.x == 0) zs[k] = mx / QMAX;
 }
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
     for (int64_t k = threadIdx.x; k < np; k += blockDim.x) {
       for (int l = 0; l < ncol; ++l) {
         if (Vd)
-          for (int q = 0; q < 4; ++q) Vd[q * vplane + kt32(j * ncol + l, k, tp * ncol)] = 0;
+          for (int q = 0; q < 4; ++q) Vd[q * vplane + kt32(vrow(j, l, ncol), k, tp * ncol)] = 0;
         if (V64) V64[(j * ncol + l) * np + k] = 0.0;
       }
       if (Dd)
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
         digits4(quantize(v[l], inv), d);
         for (int q = 0; q < 4; ++q) {
           if (l < ncol)
-            Vd[q * vplane + kt32(j * ncol + l, k, tp * ncol)] = d[q];
+            Vd[q * vplane + kt32(vrow(j, l, ncol), k, tp * ncol)] = d[q];
           else
             Dd[q * dplane + kt32(j, k, tp)] = d[q];
         }
