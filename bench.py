@@ -144,7 +144,7 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager):
     return ms, prof
 
 
-KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): ("k_grid_i8", "k_mixed.hip"),
+KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): ("k_grid32", "k_mixed.hip"),
            ("rotate", "fp64"): ("k_rot64", "k_fp64.hip"), ("grid", "fp64"): ("k_grid64", "k_fp64.hip")}
 
 
