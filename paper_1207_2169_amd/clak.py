@@ -235,7 +235,8 @@ def _block_array(blocks):
 
 
 def clak_pipeline_create(plan: int, blocks) -> int:
-    """Graph-captured pipeline over blocks = [(G, b, se[, flags]), ...]."""
+    """Two-stream pipeline over blocks = [(G, b, se[, flags]), ...]: the ingest of a block
+    overlaps the rotation and grid of the previous one."""
     arr, gdt, odt = _block_array(blocks)
     h = _P()
     _check(lib().clak_pipeline_create(ctypes.byref(h), plan, len(arr), arr, gdt, odt), "clak_pipeline_create")
@@ -251,7 +252,7 @@ def clak_pipeline_destroy(pipe: int):
 
 
 def clak_batch_create(plans, blocks_per_plan) -> int:
-    """One graph over several plans; blocks_per_plan[k] = [(G, b, se[, flags]), ...]."""
+    """One submission over several plans (cohorts); blocks_per_plan[k] = [(G, b, se[, flags]), ...]."""
     flat = [blk for bl in blocks_per_plan for blk in bl]
     arr, gdt, odt = _block_array(flat)
     ph = (_P * len(plans))(*plans)

@@ -1,4 +1,4 @@
-"""Graph-captured pipelines and cohort batches against the eager per-block
+"""Pipelines and cohort batches against the eager per-block
 path, determinism, and independence of the block split."""
 import numpy as np
 import pytest
