@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="call clak_run_block per block on one stream instead of the two-stream pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip clak_autotune (launch parameters timed on the first block before the timed region)")
+    ap.add_argument("--tune-cache", default=None, help="clak_autotune cache file (default: none, always time)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device-to-device copy of this many bytes (reference for the "
@@ -247,6 +250,13 @@ def main():
     log(f"[bench] n={w.n} p_L={w.pL} m={m} t={w.t} block={block} precision={args.precision}")
 
     plan, setup = make_plan(clak, torch, w, block, args.precision)
+    tuning = None
+    if not args.no_tune:
+        t0 = time.perf_counter()
+        clak.clak_autotune(plan.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
+        setup["autotune_ms"] = (time.perf_counter() - t0) * 1e3
+        tuning = dict(zip(("rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
+        log(f"[bench] tuned launch parameters {tuning}")
     ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager)
     cells = m * w.t
     log(f"[bench] {ms:.3f} ms/step, {cells / ms * 1e3:.4e} cells/s; stages {prof}")
@@ -280,7 +290,7 @@ def main():
         "dtype": "i8" if args.precision == "mixed" else "f64",
         "data": "synthetic (seeded generators; genotypes resident in HBM)",
         "config": {"workload": wname, "n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": m, "t": w.t, "block": block,
-                   "precision": args.precision, "parallelism": "single GPU"},
+                   "precision": args.precision, "parallelism": "single GPU", "tuning": tuning},
         "roofline": roof,
         "stage_ms_per_step": {k: v[0] for k, v in prof.items()},
         "launch": "per-block clak_run_block calls, one stream" if args.eager else

@@ -50,6 +50,9 @@ SIGNATURES = {
     "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
     "clak_plan_destroy": (_I, [_P]),
     "clak_plan_set_profiling": (_I, [_P, _I]),
+    "clak_plan_set_tuning": (_I, [_P, _I, _I, _I]),
+    "clak_plan_get_tuning": (_I, [_P, _P, _P, _P]),
+    "clak_autotune": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, ctypes.c_char_p]),
     "clak_plan_get_profile": (_I, [_P, _P, _P]),
     "clak_last_error": (ctypes.c_char_p, []),
     "clak_version": (ctypes.c_char_p, []),
@@ -178,6 +181,26 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
     blk, gdt, odt = _block_args(G, b, se, flags)
     _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags),
            "clak_run_block")
+
+
+def clak_plan_set_tuning(plan: int, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
+    _check(lib().clak_plan_set_tuning(plan, rot_rg, grid_tt, grid_xt), "clak_plan_set_tuning")
+
+
+def clak_plan_get_tuning(plan: int):
+    """(rot_rg, grid_tt, grid_xt) in effect; 0 means the built-in choice."""
+    v = [ctypes.c_int(0) for _ in range(3)]
+    _check(lib().clak_plan_get_tuning(plan, *[ctypes.cast(ctypes.byref(x), _P) for x in v]), "clak_plan_get_tuning")
+    return tuple(x.value for x in v)
+
+
+def clak_autotune(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
+                  flags: Optional[torch.Tensor] = None, cache_path: Optional[str] = None):
+    """clak_run_block that first picks (or reads from cache_path) the launch parameters."""
+    blk, gdt, odt = _block_args(G, b, se, flags)
+    cp = cache_path.encode() if cache_path is not None else None
+    _check(lib().clak_autotune(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags, cp),
+           "clak_autotune")
 
 
 def clak_plan_set_profiling(plan: int, enable: bool = True):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "clak_internal.hpp"
 
@@ -405,6 +406,127 @@ clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_
                     d_flags);
   if (s) return s;
   return ok();
+}
+
+clak_status clak_plan_set_tuning(clak_plan_t h, int rot_rg, int grid_tt, int grid_xt) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_set_tuning: null plan");
+  auto pow2_le8 = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
+  if (!pow2_le8(rot_rg) || !pow2_le8(grid_xt) || !(grid_tt == 0 || grid_tt == 32 || grid_tt == 64))
+    return fail(CLAK_E_ARG, "plan_set_tuning: rot_rg=%d grid_tt=%d grid_xt=%d outside the tunable set", rot_rg,
+                grid_tt, grid_xt);
+  p->rot_rg = rot_rg;
+  p->grid_tt = grid_tt;
+  p->grid_xt = grid_xt;
+  return ok();
+}
+
+clak_status clak_plan_get_tuning(clak_plan_t h, int* rot_rg, int* grid_tt, int* grid_xt) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_get_tuning: null plan");
+  if (rot_rg) *rot_rg = p->rot_rg;
+  if (grid_tt) *grid_tt = p->grid_tt;
+  if (grid_xt) *grid_xt = p->grid_xt;
+  return ok();
+}
+
+clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
+                          void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, const char* cache_path) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_READY, "autotune");
+  if (s) return s;
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo);
+  if (s) return s;
+  auto run = [&]() { return enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se,
+                                          out_dtype, ldo, d_flags); };
+  if (p->prec != CLAK_PREC_MIXED) {  // nothing to tune on the FP64 path
+    s = run();
+    return s ? s : ok();
+  }
+  const bool tune_grid = !p->fused_t1 && p->pL <= 3;
+  char key[160];
+  std::snprintf(key, sizeof key, "gfx950 n_pad=%lld p_L=%lld t=%lld m_blk=%lld", (long long)p->n_pad,
+                (long long)p->pL, (long long)p->t, (long long)m_blk);
+  // a cached choice for this shape
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[320];
+      bool found = false;
+      while (!found && std::fgets(line, sizeof line, f)) {
+        const size_t kl = std::strlen(key);
+        if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
+        int rg = 0, tt = 0, xt = 0;
+        if (std::sscanf(line + kl, " rot_rg=%d grid_tt=%d grid_xt=%d", &rg, &tt, &xt) == 3 &&
+            clak_plan_set_tuning(h, rg, tt, xt) == CLAK_OK)
+          found = true;
+      }
+      std::fclose(f);
+      if (found) {
+        s = run();
+        return s ? s : ok();
+      }
+    }
+  }
+  // measure: one full block fills slot 0, then each candidate launch of the
+  // rotation and of the grid kernel is timed on it (all candidates compute
+  // bitwise identical results; only the work-group-to-tile mapping differs)
+  s = run();
+  if (s) return s;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(CLAK_E_DEVICE, "autotune: event creation failed");
+  }
+  const bool prof = p->profiling;
+  p->profiling = false;
+  hipError_t err = hipSuccess;
+  auto time_ms = [&](auto&& launch) -> float {
+    float best = 1e30f;
+    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
+      err = hipEventRecord(e0, p->stream);
+      if (err == hipSuccess) err = launch();
+      if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
+      if (err == hipSuccess) err = hipEventSynchronize(e1);
+      float ms = 0.0f;
+      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+      if (err == hipSuccess && rep > 0 && ms < best) best = ms;  // the first launch warms the caches
+    }
+    return best;
+  };
+  const int pow2[4] = {1, 2, 4, 8};
+  int best_rg = 0;
+  float best_t = 1e30f;
+  for (int rg : pow2) {
+    p->rot_rg = rg;
+    const float ms = time_ms([&] { return launch_rotate_snps(*p, m_blk); });
+    if (ms < best_t) best_t = ms, best_rg = rg;
+  }
+  p->rot_rg = best_rg;
+  int best_tt = 0, best_xt = 0;
+  if (tune_grid) {
+    best_t = 1e30f;
+    for (int tt : {32, 64})
+      for (int xt : pow2) {
+        p->grid_tt = tt;
+        p->grid_xt = xt;
+        const float ms = time_ms([&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); });
+        if (ms < best_t) best_t = ms, best_tt = tt, best_xt = xt;
+      }
+  }
+  p->grid_tt = best_tt;
+  p->grid_xt = best_xt;
+  p->profiling = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (err != hipSuccess) return fail(CLAK_E_DEVICE, "autotune: %s", hipGetErrorString(err));
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s rot_rg=%d grid_tt=%d grid_xt=%d\n", key, p->rot_rg, p->grid_tt, p->grid_xt);
+      std::fclose(f);
+    }
+  }
+  s = run();  // the block's outputs, with the chosen parameters
+  return s ? s : ok();
 }
 
 clak_status clak_plan_set_profiling(clak_plan_t h, int enable) {

@@ -30,12 +30,12 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 // fragment feeds four MFMAs.  The K loop runs over 64-deep slices with LDS
 // double buffering (one barrier per slice; the next slice's global loads are
 // in flight during the current slice's MFMAs).  Work-groups are dispatched
-// round-robin over the 8 XCDs; the tiles are laid out as a 2 x 4 grid of (row
-// group, SNP group) so that XCD x owns half of the Z^T rows (which stay in its
-// L2) for a quarter of the SNP tiles, walking each SNP tile over its row tiles
-// before moving on (the genotype tile is then reused from L2).  Z^T is read
-// twice per block and the genotype panel four times, instead of eight times
-// one or the other.
+// round-robin over the 8 XCDs; the tiles are laid out as an rg x (8 / rg)
+// grid of (row group, SNP group) so that XCD x owns 1 / rg of the Z^T rows
+// (which stay in its L2) for rg / 8 of the SNP tiles, walking each SNP tile
+// over its row tiles before moving on (the genotype tile is then reused from
+// L2).  With rg = 2, Z^T is read twice per block and the genotype panel four
+// times, instead of eight times one or the other.
 // Per element, the planes are recombined exactly, scaled, and the centring
 // term (Z^T Q_L)[k] . v(i) is subtracted (FP64).  Then
 //   EPI 0: the value is stored (SNP-major) and the SNP's max |x~_k| is raised
@@ -51,11 +51,11 @@ __device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
-constexpr int ROT_RG = 2, ROT_SG = 4;  // XCD grid: row groups x SNP groups
+constexpr int ROT_RG_DEFAULT = 2;  // XCD grid: rg row groups x 8 / rg SNP groups
 
 template <int PL, int EPI, int CT, int WR, int WC>
 __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2)
-    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, const int8_t* __restrict__ Zd,
+    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, const int8_t* __restrict__ Zd,
              const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
              double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
              const double* __restrict__ Dv, double* __restrict__ part) {
@@ -67,9 +67,9 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid / WC, wc = wid % WC;
   const int64_t ntm = np / BM;
-  const int64_t gm = (ntm + ROT_RG - 1) / ROT_RG, gn = (ntn + ROT_SG - 1) / ROT_SG;
+  const int64_t sg = 8 / rg, gm = (ntm + rg - 1) / rg, gn = (ntn + sg - 1) / sg;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-  const int64_t tm = (xcd % ROT_RG) * gm + idx % gm, tn = (xcd / ROT_RG) * gn + idx / gm;
+  const int64_t tm = (xcd % rg) * gm + idx % gm, tn = (xcd / rg) * gn + idx / gm;
   if (tm >= ntm || tn >= ntn || idx >= gm * gn) return;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t zplane = np * np;
@@ -307,12 +307,13 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   const Workspace& W = p.ws;
   const int64_t ntn = roundup(m_blk, SNP_PAD) / ROT_BN, ntm = p.n_pad / ROT_BM;
-  const int64_t gm = (ntm + ROT_RG - 1) / ROT_RG, gn = (ntn + ROT_SG - 1) / ROT_SG;
+  const int rg = p.rot_rg ? p.rot_rg : ROT_RG_DEFAULT;
+  const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
   dim3 grid((unsigned)(8 * gm * gn));
   dim3 block(64 * ROT_WR * ROT_WC);
 #define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                    \
   case PLV:                                                                                                   \
-    k_rot_i8<PLV, EPI, ROT_CT, ROT_WR, ROT_WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, W.Zd, \
+    k_rot_i8<PLV, EPI, ROT_CT, ROT_WR, ROT_WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, W.Zd, \
                                                                            W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, \
                                                                            PP);                               \
     break;
@@ -654,9 +655,11 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
       const int64_t r_c = (ntn * ((p.t + c - 1) / c) + 255) / 256, r_t = (ntn * ((p.t + tt - 1) / tt) + 255) / 256;
       if (r_c * c <= r_t * tt) tt = c;
     }
+    if (p.grid_tt) tt = p.grid_tt;
     const int64_t ntt = (p.t + tt - 1) / tt;
     int xt = 1;
     while (xt < 8 && 2 * xt <= ntt) xt *= 2;
+    if (p.grid_xt) xt = p.grid_xt;
     const int64_t gt = (ntt + xt - 1) / xt, gs = (ntn + 8 / xt - 1) / (8 / xt);
     const dim3 g32((unsigned)(8 * gt * gs));
 #define CLAK_G32(PLV, TTV)                                                                                       \

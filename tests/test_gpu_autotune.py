@@ -1,0 +1,81 @@
+"""The launch-parameter tuner: every tunable choice leaves the results bitwise
+unchanged, clak_autotune computes the block like clak_run_block, writes its
+choice to the cache file and reads it back on the next call."""
+import numpy as np
+import pytest
+
+from synth import make_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(w, block):
+    import torch
+
+    from paper_1207_2169_amd import clak
+    plan = clak.Plan(w.n, w.pL, w.t, block, clak.CLAK_PREC_MIXED)
+    clak.clak_set_kinship(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Phi)).cuda())
+    clak.clak_set_covariates(plan.handle, torch.from_numpy(np.ascontiguousarray(w.XL.T)).cuda().t())
+    clak.clak_set_traits(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Y.T)).cuda().t(),
+                         torch.from_numpy(w.h2).cuda(), torch.from_numpy(w.s2).cuda())
+    return plan
+
+
+def _outputs(w):
+    import torch
+    b = torch.full((w.t, w.m), float("nan"), dtype=torch.float64, device="cuda")
+    return b, torch.full_like(b, float("nan")), torch.full((w.t, w.m), 255, dtype=torch.uint8, device="cuda")
+
+
+@pytest.mark.parametrize("t", [1, 150])
+def test_every_tuning_is_bitwise_identical(t):
+    import torch
+
+    from paper_1207_2169_amd import clak
+    w = make_workload(2, n=300, m=700, t=t, kin_cols=600)
+    print(f"tuning sweep t={t}", flush=True)
+    G = torch.from_numpy(w.genotypes(0, w.m)).cuda()
+    with _plan(w, w.m) as plan:
+        ref = _outputs(w)
+        clak.clak_run_block(plan.handle, G, *ref)
+        torch.cuda.synchronize()
+        assert bool(torch.isfinite(ref[0]).all()) and bool((ref[2] == 0).all())
+        for rg in (1, 2, 4, 8):
+            for tt in ((32, 64) if t > 1 else (0,)):
+                for xt in ((1, 2, 4, 8) if t > 1 else (0,)):
+                    clak.clak_plan_set_tuning(plan.handle, rg, tt, xt)
+                    out = _outputs(w)
+                    clak.clak_run_block(plan.handle, G, *out)
+                    torch.cuda.synchronize()
+                    for a, r in zip(out, ref):
+                        assert torch.equal(a, r), (rg, tt, xt)
+
+
+def test_autotune_matches_run_block_and_uses_cache(tmp_path):
+    import torch
+
+    from paper_1207_2169_amd import clak
+    w = make_workload(2, n=300, m=1000, t=100, kin_cols=600)
+    print("autotune", flush=True)
+    G = torch.from_numpy(w.genotypes(0, w.m)).cuda()
+    cache = tmp_path / "clak_tune.txt"
+    with _plan(w, w.m) as plan:
+        ref = _outputs(w)
+        clak.clak_run_block(plan.handle, G, *ref)
+        out = _outputs(w)
+        clak.clak_autotune(plan.handle, G, *out, cache_path=str(cache))
+        torch.cuda.synchronize()
+        for a, r in zip(out, ref):
+            assert torch.equal(a, r)
+        tuned = clak.clak_plan_get_tuning(plan.handle)
+        assert tuned[0] in (1, 2, 4, 8) and tuned[1] in (32, 64) and tuned[2] in (1, 2, 4, 8)
+        lines = cache.read_text().splitlines()
+        assert len(lines) == 1 and lines[0].startswith("gfx950 n_pad=384 p_L=3 t=100 m_blk=1000 ")
+    with _plan(w, w.m) as plan2:  # a new plan takes the cached choice without timing
+        out2 = _outputs(w)
+        clak.clak_autotune(plan2.handle, G, *out2, cache_path=str(cache))
+        torch.cuda.synchronize()
+        assert clak.clak_plan_get_tuning(plan2.handle) == tuned
+        assert cache.read_text().splitlines() == lines
+        for a, r in zip(out2, ref):
+            assert torch.equal(a, r)
