@@ -193,7 +193,7 @@ def cpu_baseline(w, b_gpu, se_gpu, target_s):
     traits = rng.choice(w.t, size=min(w.t, 2), replace=False)
 
     def run(ncell):
-        snp = rng.choice(w.m, size=ncell, replace=False)
+        snp = rng.choice(w.m, size=ncell, replace=ncell > w.m)  # small workloads: cells repeat
         tr = np.resize(traits, ncell)
         uniq, inv = np.unique(snp, return_inverse=True)
         G = np.concatenate([w.genotypes(int(s), 1) for s in uniq]).T.astype(np.float64)
