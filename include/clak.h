@@ -223,8 +223,8 @@ clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_rg, int* grid_tt, in
  * block size.  With a readable cache_path holding a line for the shape
  * (device, n_pad, p_L, t, m_blk) its choice is applied; otherwise every
  * candidate of clak_plan_set_tuning is timed with HIP events on this block
- * (three launches each of the rotation and, with several traits and p_L <= 3,
- * of the grid kernel), the fastest kept in the plan and, when cache_path is
+ * (three launches each of the rotation and, with several traits, of the grid
+ * kernel unless CLAK_OUT_FULL with p_L > 3), the fastest kept in the plan and, when cache_path is
  * not NULL, appended to that text file ("<shape> rot_rg=R grid_tt=T
  * grid_xt=X").  The block's outputs are then computed with the chosen
  * parameters, as by clak_run_block.  Synchronous.  The FP64 path has nothing

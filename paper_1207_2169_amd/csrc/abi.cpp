@@ -443,7 +443,7 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
     s = run();
     return s ? s : ok();
   }
-  const bool tune_grid = !p->fused_t1 && p->pL <= 3;
+  const bool tune_grid = !p->fused_t1 && (p->pL <= 3 || !(p->flags & CLAK_OUT_FULL));
   char key[160];
   std::snprintf(key, sizeof key, "gfx950 n_pad=%lld p_L=%lld t=%lld m_blk=%lld", (long long)p->n_pad,
                 (long long)p->pL, (long long)p->t, (long long)m_blk);

@@ -10,6 +10,8 @@
 #include "common.cuh"
 #include "schur.cuh"
 
+#include <type_traits>
+
 namespace clak {
 
 // v_mfma_i32_16x16x64_i8 lane layout (gfx950): lane l supplies 16 bytes of
@@ -555,8 +557,8 @@ __global__ void __launch_bounds__(256, 1)
              const double* __restrict__ vs, const double* __restrict__ ds, const double* __restrict__ tpar,
              const double* __restrict__ sstat, uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
              int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
-  constexpr int NV = PL + 1, NG = TT / 32;
-  static_assert(NV <= 4 && NG <= 4, "at most four accumulator tiles per wave");
+  constexpr int NV = PL + 1, NG = TT / 32, NH = (NV + 3) / 4;  // NH chunks of at most four entries
+  static_assert(NG <= 4 && NH <= 3, "at most four accumulator tiles per wave, p_L <= 11");
   __shared__ __attribute__((aligned(16))) int8_t smem[2 * G32_STAGE];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8, xs = 8 / xt;
@@ -593,10 +595,56 @@ __global__ void __launch_bounds__(256, 1)
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[u][e] = (v16i){};
-    g32_pass<NV>(acc, smem, pa, xplane, mbp * 32, Vd + wid * vplane + vrow(j0 + 32 * g, 0, NV) * 32 + lchunk,
-                 vrows * 32, KT, afrag, bfrag);
     // lane: trait j0 + 32 g + lane % 32, SNP rows 8 (r / 4) + 4 (lane / 32) + r % 4 of the wave's tile
     const int64_t j = j0 + 32 * g + (lane & 31);
+    const int8_t* pv = Vd + wid * vplane + vrow(j0 + 32 * g, 0, NV) * 32 + lchunk;
+    if constexpr (NH > 1) {
+      // more than four entries: passes over chunks of four, ||c'||^2 carried
+      // in FP64 between them (SNP effect and SE only; the full vector takes
+      // the 16x16x64 kernel)
+      double ccp[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) ccp[r] = 0.0;
+      auto chunk = [&](auto hc) {
+        constexpr int H = decltype(hc)::value, NT = (NV - 4 * H) < 4 ? (NV - 4 * H) : 4;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) acc[u][e] = (v16i){};
+        g32_pass<NT>(acc, smem, pa, xplane, mbp * 32, pv + 128 * 32 * H, vrows * 32, KT, afrag, bfrag);
+        if (j >= t) return;
+        double sc[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) sc[u] = vs[j * NV + 4 * H + u] * (1.0 / 127.0);
+        const double sd = ds[j] * (1.0 / 127.0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t i = i0 + 32 * wid + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          if (i < m_blk) {
+            const double* st = sstat + i * ss;
+            const double gx = st[2 * PL + 2];
+            double rr = 0.0;
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+              const double v = g32_value(acc[u], r) * sc[u] * gx;
+              if (4 * H + u < PL)
+                ccp[r] += v * v;
+              else
+                rr = v;
+            }
+            if (H == NH - 1)
+              schur_store_cc<PL>(ccp[r], rr, araw[g][r] * sd * gx * gx, tpar + j * trait_stride(PL), st, flags, i,
+                                 j, ob, ose, out_f64, ldo, oflags);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      };
+      chunk(std::integral_constant<int, 0>{});
+      chunk(std::integral_constant<int, 1>{});
+      if constexpr (NH > 2) chunk(std::integral_constant<int, 2>{});
+      continue;
+    }
+    g32_pass<NV>(acc, smem, pa, xplane, mbp * 32, pv, vrows * 32, KT, afrag, bfrag);
     if (j < t) {
       double sc[NV];
 #pragma unroll
@@ -646,7 +694,7 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
   const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;
   if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
-  if (p.pL <= 3) {
+  if (p.pL <= 3 || !(p.flags & CLAK_OUT_FULL)) {
     // traits per work-group: 64 unless 32 gives fewer modelled
     // dispatch rounds of 256 work-groups x traits per tile
     const int64_t ntn = (m_blk + G32_BM - 1) / G32_BM;
@@ -674,7 +722,7 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
       CLAK_G32(PLV, 64); \
     break;
     switch (p.pL) {
-      CLAK_G32T(1) CLAK_G32T(2) CLAK_G32T(3)
+      CLAK_G32T(1) CLAK_G32T(2) CLAK_G32T(3) CLAK_G32T(4) CLAK_G32T(5) CLAK_G32T(6) CLAK_G32T(7) CLAK_G32T(8)
       default:
         return hipErrorInvalidValue;
     }

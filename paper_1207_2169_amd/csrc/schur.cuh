@@ -63,4 +63,30 @@ __device__ __forceinline__ void schur_store(const double* c, double r, double a,
   if (oflags) oflags[o] = (uint8_t)flag;
 }
 
+// The SNP-effect form of schur_store when ||c'||^2 has been accumulated in
+// pieces (cc): b_snp, SE and the flag of the cell.
+template <int PL>
+__device__ __forceinline__ void schur_store_cc(double cc, double r, double a, const double* __restrict__ tp,
+                                               const double* __restrict__ st, uint32_t flags, int64_t i, int64_t j,
+                                               void* __restrict__ ob, void* __restrict__ ose, int out_f64,
+                                               int64_t ldo, uint8_t* __restrict__ oflags) {
+  int flag = (int)st[2 * PL + 1];
+  const double s = a - cc;
+  if (flag == 0 && !(s > 1e-10 * a)) flag = CLAK_CELL_DEGENERATE;
+  double bsnp = __builtin_nan(""), se = __builtin_nan("");
+  if (flag == 0) {
+    bsnp = r / s;
+    se = sqrt((flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] / s : 1.0 / s);
+  }
+  const int64_t o = i + j * ldo;
+  if (out_f64) {
+    ((double*)ob)[o] = bsnp;
+    ((double*)ose)[o] = se;
+  } else {
+    ((float*)ob)[o] = (float)bsnp;
+    ((float*)ose)[o] = (float)se;
+  }
+  if (oflags) oflags[o] = (uint8_t)flag;
+}
+
 }  // namespace clak

@@ -67,12 +67,14 @@ def test_mixed_wide_trait_tiles_sampled():
     assert eb < TOL and es < TOL
 
 
-def test_mixed_full_vector_and_paper_variance():
+@pytest.mark.parametrize("cfg,kw", [(2, dict(n=200, m=70, t=5, kin_cols=400)),
+                                    (4, dict(n=300, m=90, t=6, kin_cols=600))])
+def test_mixed_full_vector_and_paper_variance(cfg, kw):
     from paper_1207_2169_amd import clak
-    w = make_workload(2, n=200, m=70, t=5, kin_cols=400)
+    w = make_workload(cfg, **kw)
     flags = clak.CLAK_OUT_FULL | clak.CLAK_VAR_PAPER
-    print("mixed full vector / paper variance", flush=True)
-    b, se, fl = gpu_run(w, clak.CLAK_PREC_MIXED, flags=flags, block=70, g_dtype="f16")
+    print(f"mixed full vector / paper variance cfg={cfg} p_L={w.pL}", flush=True)
+    b, se, fl = gpu_run(w, clak.CLAK_PREC_MIXED, flags=flags, block=w.m, g_dtype="f16")
     ii, jj = _all_cells(w.m, w.t)
     rb, rse, rfl = oracle_cells(w, ii, jj, var_paper=True)
     bf = b.reshape(-1, w.pL + 1)
