@@ -259,7 +259,7 @@ def main():
         t0 = time.perf_counter()
         clak.clak_autotune(plan.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
         setup["autotune_ms"] = (time.perf_counter() - t0) * 1e3
-        tuning = dict(zip(("rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
+        tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
         log(f"[bench] tuned launch parameters {tuning}")
     ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager)
     cells = m * w.t

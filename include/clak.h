@@ -208,16 +208,18 @@ clak_status clak_batch_launch(clak_batch_t batch, void* hip_stream);
 clak_status clak_batch_destroy(clak_batch_t batch);
 
 /* Launch parameters of the mixed path's kernels, all of which leave every
- * result bitwise unchanged (they only map work-groups to tiles):
+ * result bitwise unchanged (they only change how tiles map to work-groups):
+ *   rot_cfg : the rotation's tile configuration, 64-row tiles of 128 or 256
+ *             SNPs with two, four or eight waves (0 to 3);
  *   rot_rg  : the rotation's XCD row groups (1, 2, 4, 8; the 8 XCDs split into
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
  *   grid_tt : traits per work-group of the grid contraction (32 or 64);
  *   grid_xt : XCD trait groups of the grid contraction (1, 2, 4, 8).
  * 0 selects the built-in choice.  Errors: CLAK_E_ARG for other values. */
-clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_rg, int grid_tt, int grid_xt);
+clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
 /* The launch parameters in effect (0: built-in choice); null outputs skipped. */
-clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_rg, int* grid_tt, int* grid_xt);
+clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, int* grid_tt, int* grid_xt);
 
 /* clak_run_block that first picks the launch parameters for this plan and
  * block size.  With a readable cache_path holding a line for the shape
@@ -225,9 +227,9 @@ clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_rg, int* grid_tt, in
  * candidate of clak_plan_set_tuning is timed with HIP events on this block
  * (three launches each of the rotation and, with several traits, of the grid
  * kernel unless CLAK_OUT_FULL with p_L > 3), the fastest kept in the plan and, when cache_path is
- * not NULL, appended to that text file ("<shape> rot_rg=R grid_tt=T
- * grid_xt=X").  The block's outputs are then computed with the chosen
- * parameters, as by clak_run_block.  Synchronous.  The FP64 path has nothing
+ * not NULL, appended to that text file ("<shape> rot_cfg=C rot_rg=R
+ * grid_tt=T grid_xt=X").  The block's outputs are then computed with the
+ * chosen parameters, as by clak_run_block.  Synchronous.  The FP64 path has nothing
  * to tune and runs the block.  Errors: as clak_run_block, CLAK_E_DEVICE. */
 clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, const char* cache_path);

@@ -50,8 +50,8 @@ SIGNATURES = {
     "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
     "clak_plan_destroy": (_I, [_P]),
     "clak_plan_set_profiling": (_I, [_P, _I]),
-    "clak_plan_set_tuning": (_I, [_P, _I, _I, _I]),
-    "clak_plan_get_tuning": (_I, [_P, _P, _P, _P]),
+    "clak_plan_set_tuning": (_I, [_P, _I, _I, _I, _I]),
+    "clak_plan_get_tuning": (_I, [_P, _P, _P, _P, _P]),
     "clak_autotune": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, ctypes.c_char_p]),
     "clak_plan_get_profile": (_I, [_P, _P, _P]),
     "clak_last_error": (ctypes.c_char_p, []),
@@ -183,13 +183,13 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
            "clak_run_block")
 
 
-def clak_plan_set_tuning(plan: int, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
-    _check(lib().clak_plan_set_tuning(plan, rot_rg, grid_tt, grid_xt), "clak_plan_set_tuning")
+def clak_plan_set_tuning(plan: int, rot_cfg: int = 0, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
+    _check(lib().clak_plan_set_tuning(plan, rot_cfg, rot_rg, grid_tt, grid_xt), "clak_plan_set_tuning")
 
 
 def clak_plan_get_tuning(plan: int):
-    """(rot_rg, grid_tt, grid_xt) in effect; 0 means the built-in choice."""
-    v = [ctypes.c_int(0) for _ in range(3)]
+    """(rot_cfg, rot_rg, grid_tt, grid_xt) in effect; 0 means the built-in choice."""
+    v = [ctypes.c_int(0) for _ in range(4)]
     _check(lib().clak_plan_get_tuning(plan, *[ctypes.cast(ctypes.byref(x), _P) for x in v]), "clak_plan_get_tuning")
     return tuple(x.value for x in v)
 

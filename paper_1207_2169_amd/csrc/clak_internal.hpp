@@ -113,9 +113,9 @@ struct Plan {
   int state = ST_CREATED;
   bool fused_t1 = false;    // single trait: rotate-and-reduce kernel, no stored X~
   // launch parameters chosen by clak_autotune or clak_plan_set_tuning (0: the
-  // built-in choice): XCD row groups of the rotation, traits per work-group
-  // and XCD trait groups of the grid contraction
-  int rot_rg = 0, grid_tt = 0, grid_xt = 0;
+  // built-in choice): rotation tile configuration and XCD row groups, traits
+  // per work-group and XCD trait groups of the grid contraction
+  int rot_cfg = 0, rot_rg = 0, grid_tt = 0, grid_xt = 0;
   // stage profiler: pending (stage, start, end) event triples and totals
   bool profiling = false;
   struct Timed {

@@ -240,10 +240,15 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
 }
 
 // Rotation tile configuration: CT 32-column MFMA tiles per wave, WR x WC waves.
-constexpr int ROT_CT = 2, ROT_WR = 2, ROT_WC = 2;
-constexpr int ROT_BM = 32 * ROT_WR;
-constexpr int ROT_BN = 32 * ROT_CT * ROT_WC;
-static_assert(SNP_PAD % ROT_BN == 0 && KPAD % ROT_BM == 0, "rotation tile must divide the paddings");
+// Rotation tile configurations (CT, WR, WC), all with 64-row tiles so that the
+// single-trait partials (one per 64-row tile, combined over the WR = 2 wave
+// rows in a fixed order) are bitwise the same whichever is chosen:
+//   0: 2, 2, 2   64 x 128 tile, 4 waves (two work-groups per CU)
+//   1: 4, 2, 1   64 x 128 tile, 2 waves, four column tiles per wave
+//   2: 2, 2, 4   64 x 256 tile, 8 waves
+//   3: 4, 2, 2   64 x 256 tile, 4 waves, four column tiles per wave
+constexpr int ROT_BM = 64, ROT_NCFG = 4;
+static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0, "rotation tiles must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
 // order and solves the cell (Schur complement, FP64).  A work-group takes 64
@@ -306,18 +311,20 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
   for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + off) = pk[q];
 }
 
-hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
+template <int CT, int WR, int WC>
+static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
+  constexpr int BN = 32 * CT * WC;
+  static_assert(32 * WR == ROT_BM && SNP_PAD % BN == 0, "rotation tile");
   const Workspace& W = p.ws;
-  const int64_t ntn = roundup(m_blk, SNP_PAD) / ROT_BN, ntm = p.n_pad / ROT_BM;
+  const int64_t ntn = roundup(m_blk, SNP_PAD) / BN, ntm = p.n_pad / ROT_BM;
   const int rg = p.rot_rg ? p.rot_rg : ROT_RG_DEFAULT;
   const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
   dim3 grid((unsigned)(8 * gm * gn));
-  dim3 block(64 * ROT_WR * ROT_WC);
-#define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                    \
-  case PLV:                                                                                                   \
-    k_rot_i8<PLV, EPI, ROT_CT, ROT_WR, ROT_WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, W.Zd, \
-                                                                           W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, \
-                                                                           PP);                               \
+  dim3 block(64 * WR * WC);
+#define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                         \
+  case PLV:                                                                                                        \
+    k_rot_i8<PLV, EPI, CT, WR, WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, W.Zd, W.zs,     \
+                                                                 W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);             \
     break;
   if (p.fused_t1) {
     switch (p.pL) {
@@ -338,6 +345,19 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   }
 #undef CLAK_ROT
   return hipGetLastError();
+}
+
+hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
+  switch (p.rot_cfg) {
+    case 1:
+      return rotate_cfg<4, 2, 1>(p, m_blk);
+    case 2:
+      return rotate_cfg<2, 2, 4>(p, m_blk);
+    case 3:
+      return rotate_cfg<4, 2, 2>(p, m_blk);
+    default:
+      return rotate_cfg<2, 2, 2>(p, m_blk);
+  }
 }
 
 hipError_t launch_encode(const Plan& p, int64_t m_blk) {
