@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="call clak_run_block per block on one stream instead of the two-stream pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--host-genotypes", action="store_true",
+                    help="keep the genotypes in pinned host memory: the ingest kernel reads them over PCIe "
+                         "(end-to-end rate with the host link; not the HBM-resident headline)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip clak_autotune (launch parameters timed on the first block before the timed region)")
     ap.add_argument("--tune-cache", default=None, help="clak_autotune cache file (default: none, always time)")
@@ -61,9 +64,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def upload_genotypes(w, m, torch):
-    """(m, n) uint8 genotypes on the GPU, generated block by block on the host."""
-    G = torch.empty((m, w.n), dtype=torch.uint8, device="cuda")
+def upload_genotypes(w, m, torch, host=False):
+    """(m, n) uint8 genotypes on the GPU (or in pinned host memory), generated block by block on the host."""
+    G = torch.empty((m, w.n), dtype=torch.uint8, pin_memory=True) if host else \
+        torch.empty((m, w.n), dtype=torch.uint8, device="cuda")
     chunk = 100_000
     for s0 in range(0, m, chunk):
         c = min(chunk, m - s0)
@@ -248,10 +252,11 @@ def main():
     w = make_workload(cfg, **kw)
     block = w.block
     m = w.m
-    G = upload_genotypes(w, m, torch)
+    G = upload_genotypes(w, m, torch, host=args.host_genotypes)
     b = torch.empty((w.t, m), dtype=torch.float32, device="cuda")
     se = torch.empty_like(b)
-    log(f"[bench] n={w.n} p_L={w.pL} m={m} t={w.t} block={block} precision={args.precision}")
+    log(f"[bench] n={w.n} p_L={w.pL} m={m} t={w.t} block={block} precision={args.precision}"
+        + (" genotypes in pinned host memory" if args.host_genotypes else ""))
 
     plan, setup = make_plan(clak, torch, w, block, args.precision)
     tuning = None
@@ -292,7 +297,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i8" if args.precision == "mixed" else "f64",
-        "data": "synthetic (seeded generators; genotypes resident in HBM)",
+        "data": "synthetic (seeded generators; genotypes " + ("in pinned host memory, read over PCIe by the ingest "
+                "kernel)" if args.host_genotypes else "resident in HBM)"),
         "config": {"workload": wname, "n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": m, "t": w.t, "block": block,
                    "precision": args.precision, "parallelism": "single GPU", "tuning": tuning},
         "roofline": roof,

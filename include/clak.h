@@ -15,8 +15,12 @@
  *
  * Conventions
  *   - Every pointer argument named d_* is a DEVICE pointer on the device that
- *     was current when the plan was created.  All matrices are column-major
- *     with an explicit leading dimension; all sizes are int64_t.
+ *     was current when the plan was created, or a pointer to pinned host
+ *     memory that the device sees at the same address (hipHostMalloc); a
+ *     genotype block there is read over PCIe by the ingest kernel.  Any other
+ *     pointer (pageable host memory, another device's memory) is refused with
+ *     CLAK_E_ARG before any device work.  All matrices are column-major with
+ *     an explicit leading dimension; all sizes are int64_t.
  *   - The caller owns every buffer it passes in (inputs, outputs and the
  *     workspace).  The library owns only the opaque plan (host memory plus a
  *     rocBLAS handle), released by clak_plan_destroy.  It never frees caller

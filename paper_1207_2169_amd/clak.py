@@ -105,8 +105,10 @@ def _check(status: int, where: str):
 
 
 def _dev(x: torch.Tensor, what: str, dtype=None):
-    if not isinstance(x, torch.Tensor) or not x.is_cuda:
-        raise ValueError(f"{what} must be a torch tensor on the GPU")
+    """A GPU tensor, or a pinned host tensor (the library reads it over PCIe; it
+    refuses memory the device cannot address)."""
+    if not isinstance(x, torch.Tensor) or not (x.is_cuda or x.is_pinned()):
+        raise ValueError(f"{what} must be a torch tensor on the GPU or in pinned host memory")
     if dtype is not None and x.dtype != dtype:
         raise ValueError(f"{what} must be {dtype}, got {x.dtype}")
     return x
@@ -143,6 +145,8 @@ def clak_plan_workspace_size(plan: int) -> int:
 
 
 def clak_plan_set_workspace(plan: int, ws: torch.Tensor):
+    if not ws.is_cuda:
+        raise ValueError("the workspace must be a GPU tensor")
     _dev(ws, "workspace", torch.uint8)
     _check(lib().clak_plan_set_workspace(plan, ws.data_ptr(), ws.numel()), "clak_plan_set_workspace")
 

@@ -53,6 +53,26 @@ clak_status need_state(const Plan* p, int min_state, const char* what) {
 
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
+// True when the kernels of this device may dereference ptr: device memory of
+// the plan's device, managed memory, or pinned host memory mapped at the same
+// address.  Pageable host memory (which a kernel access would fault on) and
+// unknown pointers are refused before anything is launched.
+bool device_accessible(const Plan* p, const void* ptr) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  if (a.isManaged) return true;
+  if (a.type == hipMemoryTypeDevice) return a.device == p->device;
+  if (a.type == hipMemoryTypeHost) {  // the device address of ptr must be ptr itself
+    if (!a.devicePointer || !a.hostPointer) return false;
+    const char* dp = (const char*)a.devicePointer + ((const char*)ptr - (const char*)a.hostPointer);
+    return dp == (const char*)ptr;
+  }
+  return a.type == hipMemoryTypeUnified || a.type == hipMemoryTypeManaged;
+}
+
 hipEvent_t take_event(Plan* p) {
   if (!p->event_pool.empty()) {
     hipEvent_t e = p->event_pool.back();
@@ -211,6 +231,11 @@ clak_status clak_plan_set_workspace(clak_plan_t h, void* d_ws, size_t bytes) {
   if (!p) return fail(CLAK_E_ARG, "plan_set_workspace: null plan");
   if (!d_ws) return fail(CLAK_E_WORKSPACE, "plan_set_workspace: null workspace");
   if (!aligned(d_ws, 256)) return fail(CLAK_E_WORKSPACE, "plan_set_workspace: workspace not 256-byte aligned");
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, d_ws) != hipSuccess || a.type != hipMemoryTypeDevice || a.device != p->device) {
+    (void)hipGetLastError();
+    return fail(CLAK_E_WORKSPACE, "plan_set_workspace: the workspace must be device memory of the plan's device");
+  }
   size_t need = workspace_bytes(*p, nullptr, nullptr);
   if (bytes < need)
     return fail(CLAK_E_WORKSPACE, "plan_set_workspace: %zu bytes given, %zu needed", bytes, need);
@@ -244,6 +269,7 @@ clak_status clak_set_kinship(clak_plan_t h, const double* d_Phi, int64_t ld) {
   clak_status s = need_state(p, ST_WS, "set_kinship");
   if (s) return s;
   if (!d_Phi) return fail(CLAK_E_ARG, "set_kinship: null Phi");
+  if (!device_accessible(p, d_Phi)) return fail(CLAK_E_ARG, "set_kinship: Phi is not device-accessible memory");
   if (ld < p->n) return fail(CLAK_E_ARG, "set_kinship: ld=%lld < n", (long long)ld);
   p->state = ST_WS;
   const int64_t n = p->n, np = p->n_pad;
@@ -271,6 +297,8 @@ clak_status clak_set_eigen(clak_plan_t h, const double* d_Z, int64_t ldz, const 
   clak_status s = need_state(p, ST_WS, "set_eigen");
   if (s) return s;
   if (!d_Z || !d_w) return fail(CLAK_E_ARG, "set_eigen: null Z or w");
+  if (!device_accessible(p, d_Z) || !device_accessible(p, d_w))
+    return fail(CLAK_E_ARG, "set_eigen: Z or w is not device-accessible memory");
   if (ldz < p->n) return fail(CLAK_E_ARG, "set_eigen: ldz=%lld < n", (long long)ldz);
   p->state = ST_WS;
   const int64_t n = p->n, np = p->n_pad;
@@ -289,6 +317,7 @@ clak_status clak_set_covariates(clak_plan_t h, const double* d_XL, int64_t ld) {
   clak_status s = need_state(p, ST_EIG, "set_covariates");
   if (s) return s;
   if (!d_XL) return fail(CLAK_E_ARG, "set_covariates: null X_L");
+  if (!device_accessible(p, d_XL)) return fail(CLAK_E_ARG, "set_covariates: X_L is not device-accessible memory");
   if (ld < p->n) return fail(CLAK_E_ARG, "set_covariates: ld=%lld < n", (long long)ld);
   p->state = ST_EIG;
   Workspace& W = p->ws;
@@ -310,6 +339,8 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   clak_status s = need_state(p, ST_COV, "set_traits");
   if (s) return s;
   if (!d_Y || !d_h2 || !d_s2) return fail(CLAK_E_ARG, "set_traits: null Y, h2 or s2");
+  if (!device_accessible(p, d_Y) || !device_accessible(p, d_h2) || !device_accessible(p, d_s2))
+    return fail(CLAK_E_ARG, "set_traits: Y, h2 or s2 is not device-accessible memory");
   if (ldy < p->n) return fail(CLAK_E_ARG, "set_traits: ldy=%lld < n", (long long)ldy);
   p->state = ST_COV;
   Workspace& W = p->ws;
@@ -341,7 +372,7 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
 namespace clak {
 
 clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
-                           const void* d_se, int out_dtype, int64_t ldo) {
+                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags) {
   if (m_blk < 1 || m_blk > p->max_block)
     return fail(CLAK_E_ARG, "run_block: m_blk=%lld outside [1, max_block=%lld]", (long long)m_blk,
                 (long long)p->max_block);
@@ -354,6 +385,9 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
   const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
   if (!aligned(d_b, esz) || !aligned(d_se, esz)) return fail(CLAK_E_ARG, "run_block: misaligned output");
   if (g_dtype == CLAK_G_F16 && !aligned(d_G, 2)) return fail(CLAK_E_ARG, "run_block: misaligned F16 genotypes");
+  if (!device_accessible(p, d_G)) return fail(CLAK_E_ARG, "run_block: G is not device-accessible memory");
+  if (!device_accessible(p, d_b) || !device_accessible(p, d_se) || (d_flags && !device_accessible(p, d_flags)))
+    return fail(CLAK_E_ARG, "run_block: an output is not device-accessible memory");
   return CLAK_OK;
 }
 
@@ -400,7 +434,7 @@ clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_READY, "run_block");
   if (s) return s;
-  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo);
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags);
   if (s) return s;
   s = enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo,
                     d_flags);
@@ -438,7 +472,7 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_READY, "autotune");
   if (s) return s;
-  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo);
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags);
   if (s) return s;
   auto run = [&]() { return enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se,
                                           out_dtype, ldo, d_flags); };

@@ -155,8 +155,9 @@ inline void select_slot(Plan& p, int k) {
 clak_status fail(clak_status s, const char* fmt, ...);
 clak_status ok();
 clak_status need_state(const Plan* p, int min_state, const char* what);
+bool device_accessible(const Plan* p, const void* ptr);
 clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
-                           const void* d_se, int out_dtype, int64_t ldo);
+                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags);
 clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
                           int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b, void* d_se,
                           int out_dtype, int64_t ldo, uint8_t* d_flags);

@@ -109,7 +109,7 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
 clak_status check_blocks(Plan* p, int64_t n, const clak_block* blocks, int g_dtype, int out_dtype) {
   for (int64_t b = 0; b < n; ++b) {
     const clak_block& B = blocks[b];
-    clak_status s = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo);
+    clak_status s = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags);
     if (s) return s;
   }
   return CLAK_OK;

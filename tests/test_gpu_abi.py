@@ -140,3 +140,37 @@ def test_degenerate_and_bad_genotypes(w, prec):
     rse = np.sqrt(rv[:, -1, -1])
     assert np.max(np.abs(b[4:] - rb[:, -1]) / rse) < tol
     assert np.max(np.abs(se[4:] - rse) / rse) < tol
+
+
+def test_pinned_host_genotypes_and_pageable_refusal():
+    """A genotype block in pinned host memory (read over PCIe by the ingest
+    kernel) gives bitwise the same cells as one in device memory; pageable host
+    memory is refused with CLAK_E_ARG before anything is launched."""
+    import ctypes
+
+    import torch
+
+    from paper_1207_2169_amd import clak
+    w = make_workload(2, n=300, m=500, t=7, kin_cols=600)
+    print("pinned host genotypes", flush=True)
+    g = torch.from_numpy(w.genotypes(0, w.m))
+    with clak.Plan(w.n, w.pL, w.t, w.m, clak.CLAK_PREC_MIXED) as plan:
+        clak.clak_set_kinship(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Phi)).cuda())
+        clak.clak_set_covariates(plan.handle, torch.from_numpy(np.ascontiguousarray(w.XL.T)).cuda().t())
+        clak.clak_set_traits(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Y.T)).cuda().t(),
+                             torch.from_numpy(w.h2).cuda(), torch.from_numpy(w.s2).cuda())
+        outs = []
+        for G in (g.cuda(), g.pin_memory()):
+            b = torch.full((w.t, w.m), float("nan"), dtype=torch.float64, device="cuda")
+            se = torch.full_like(b, float("nan"))
+            clak.clak_run_block(plan.handle, G, b, se)
+            torch.cuda.synchronize()
+            outs.append((b, se))
+        assert torch.isfinite(outs[0][0]).all()
+        assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+        b, se = outs[0]
+        st = clak.lib().clak_run_block(plan.handle, w.m, ctypes.c_void_p(g.data_ptr()), clak.CLAK_G_U8, w.n,
+                                       ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(se.data_ptr()),
+                                       clak.CLAK_OUT_F64, w.m, None)
+        assert st == clak.CLAK_E_ARG
+        assert b"device-accessible" in clak.lib().clak_last_error()
