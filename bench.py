@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--host-genotypes", action="store_true",
                     help="keep the genotypes in pinned host memory: the ingest kernel reads them over PCIe "
                          "(end-to-end rate with the host link; not the HBM-resident headline)")
+    ap.add_argument("--stage-genotypes", action="store_true",
+                    help="plan flag CLAK_STAGE_GENOTYPES: copy-engine staging of every block before the ingest")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip clak_autotune (launch parameters timed on the first block before the timed region)")
     ap.add_argument("--tune-cache", default=None, help="clak_autotune cache file (default: none, always time)")
@@ -102,9 +104,9 @@ class Pass:
             self.pipe = None
 
 
-def make_plan(clak, torch, w, block, precision):
+def make_plan(clak, torch, w, block, precision, flags=0):
     prec = clak.CLAK_PREC_MIXED if precision == "mixed" else clak.CLAK_PREC_FP64
-    plan = clak.Plan(w.n, w.pL, w.t, block, prec)
+    plan = clak.Plan(w.n, w.pL, w.t, block, prec, flags)
     t = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -258,7 +260,8 @@ def main():
     log(f"[bench] n={w.n} p_L={w.pL} m={m} t={w.t} block={block} precision={args.precision}"
         + (" genotypes in pinned host memory" if args.host_genotypes else ""))
 
-    plan, setup = make_plan(clak, torch, w, block, args.precision)
+    plan, setup = make_plan(clak, torch, w, block, args.precision,
+                            clak.CLAK_STAGE_GENOTYPES if (args.host_genotypes or args.stage_genotypes) else 0)
     tuning = None
     if not args.no_tune:
         t0 = time.perf_counter()
@@ -297,8 +300,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "i8" if args.precision == "mixed" else "f64",
-        "data": "synthetic (seeded generators; genotypes " + ("in pinned host memory, read over PCIe by the ingest "
-                "kernel)" if args.host_genotypes else "resident in HBM)"),
+        "data": "synthetic (seeded generators; genotypes " + ("in pinned host memory, copied block by block over "
+                "PCIe by the copy engine on the ingest stream)" if args.host_genotypes else "resident in HBM)"),
         "config": {"workload": wname, "n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": m, "t": w.t, "block": block,
                    "precision": args.precision, "parallelism": "single GPU", "tuning": tuning},
         "roofline": roof,

@@ -82,6 +82,13 @@ typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_pre
 #define CLAK_VAR_PAPER 1u   /* Var(b) = s2_j (X^T M^{-1} X)^{-1}, as printed        */
 #define CLAK_OUT_SNP 0u     /* write the SNP effect b_ij[p-1] only                 */
 #define CLAK_OUT_FULL 2u    /* write all p components of b_ij                      */
+#define CLAK_STAGE_GENOTYPES 4u /* reserve a staging buffer per workspace slot: every
+                                   genotype block is first copied there by the copy
+                                   engine on the ingest stream (over PCIe from pinned
+                                   host memory, within HBM from device memory) into
+                                   16-byte-aligned rows, then ingested.  Without the
+                                   flag the ingest kernel reads the caller's block,
+                                   also a pinned host block over PCIe.            */
 
 /* Genotype element types accepted by clak_run_block (values 0, 1, 2). */
 #define CLAK_G_U8 0

@@ -150,6 +150,7 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
     if (p.fused_t1) S.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
     if (!p.fused_t1) S.X64 = (double*)take(8 * mb * np);
     if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) S.Xd = (int8_t*)take(8 * mb * np);
+    if (p.flags & CLAK_STAGE_GENOTYPES) S.Gh = (uint8_t*)take(p.max_block * host_pitch(p.n));
   }
   if (w) {
     const Slot& S = W.slot[0];
@@ -181,7 +182,8 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   if (max_block < 1) return fail(CLAK_E_ARG, "plan_create: max_block must be >= 1");
   if (precision != CLAK_PREC_FP64 && precision != CLAK_PREC_MIXED)
     return fail(CLAK_E_ARG, "plan_create: unknown precision %d", precision);
-  if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL)) return fail(CLAK_E_ARG, "plan_create: unknown flags 0x%x", flags);
+  if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL | CLAK_STAGE_GENOTYPES))
+    return fail(CLAK_E_ARG, "plan_create: unknown flags 0x%x", flags);
   if (precision == CLAK_PREC_MIXED && p_L > 8)
     return fail(CLAK_E_UNSUPPORTED, "plan_create: mixed precision supports p_L <= 8");
   if (precision == CLAK_PREC_MIXED && n > MIXED_MAX_N)
@@ -410,7 +412,23 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
   };
   hipError_t e;
   p->stream = s_in;
-  e = staged(CLAK_STAGE_INGEST, [&] { return launch_ingest(*p, m_blk, d_G, g_dtype, ldg); });
+  // CLAK_STAGE_GENOTYPES: the copy engine moves the block into the slot's staging buffer, the ingest reads it there
+  const void* G = d_G;
+  int64_t ld = ldg;
+  const int64_t esz = g_dtype == CLAK_G_F16 ? 2 : 1;
+  const bool stage_copy = p->ws.slot[slot].Gh != nullptr;
+  if (stage_copy) {
+    G = p->ws.slot[slot].Gh;
+    ld = host_pitch(p->n) / esz;
+  }
+  e = staged(CLAK_STAGE_INGEST, [&] {
+    if (stage_copy) {
+      hipError_t c = hipMemcpy2DAsync(p->ws.slot[slot].Gh, host_pitch(p->n), d_G, ldg * esz, p->n * esz, m_blk,
+                                      hipMemcpyDefault, p->stream);
+      if (c != hipSuccess) return c;
+    }
+    return launch_ingest(*p, m_blk, G, g_dtype, ld);
+  });
   if (e == hipSuccess && ingested) e = hipEventRecord(ingested, s_in);
   if (e == hipSuccess && ingested && s_main != s_in) e = hipStreamWaitEvent(s_main, ingested, 0);
   p->stream = s_main;

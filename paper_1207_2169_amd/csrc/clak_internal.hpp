@@ -60,8 +60,12 @@ struct Slot {
   double* part = nullptr;
   double* X64 = nullptr;
   int8_t* Xd = nullptr;
+  uint8_t* Gh = nullptr;  // CLAK_STAGE_GENOTYPES: copy of the caller's genotype block, rows of host_pitch bytes
 };
 constexpr int NSLOTS = 2;
+
+// Row pitch (bytes) of the host-block staging buffer: n elements of up to 2 bytes, 16-byte aligned rows.
+inline int64_t host_pitch(int64_t n) { return (2 * n + 15) / 16 * 16; }
 
 struct Workspace {
   Slot slot[NSLOTS];

@@ -174,3 +174,15 @@ def test_pinned_host_genotypes_and_pageable_refusal():
                                        clak.CLAK_OUT_F64, w.m, None)
         assert st == clak.CLAK_E_ARG
         assert b"device-accessible" in clak.lib().clak_last_error()
+    # with CLAK_STAGE_GENOTYPES every block goes through the copy engine into a staging buffer
+    with clak.Plan(w.n, w.pL, w.t, w.m, clak.CLAK_PREC_MIXED, clak.CLAK_STAGE_GENOTYPES) as plan:
+        clak.clak_set_kinship(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Phi)).cuda())
+        clak.clak_set_covariates(plan.handle, torch.from_numpy(np.ascontiguousarray(w.XL.T)).cuda().t())
+        clak.clak_set_traits(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Y.T)).cuda().t(),
+                             torch.from_numpy(w.h2).cuda(), torch.from_numpy(w.s2).cuda())
+        for G in (g.pin_memory(), g.half().pin_memory(), g.cuda(), g.half().cuda()):
+            b = torch.full((w.t, w.m), float("nan"), dtype=torch.float64, device="cuda")
+            se = torch.full_like(b, float("nan"))
+            clak.clak_run_block(plan.handle, G, b, se)
+            torch.cuda.synchronize()
+            assert torch.equal(b, outs[0][0]) and torch.equal(se, outs[0][1])
