@@ -128,8 +128,8 @@ clak_status clak_plan_set_workspace(clak_plan_t plan, void* d_ws, size_t bytes);
  * kernel of the plan is enqueued. */
 clak_status clak_plan_set_stream(clak_plan_t plan, void* hip_stream);
 
-/* Step 1 of the CLAK-Eig listing: Phi = Z W Z^T by the FP64 rocSOLVER divide
- * and conquer eigensolver, then the int8 digit planes of Z^T (MIXED).
+/* The eigendecomposition that opens CLAK-Eig (section 3): Phi = Z W Z^T by the
+ * FP64 rocSOLVER divide and conquer eigensolver, then the int8 digit planes of Z^T (MIXED).
  * d_Phi: n x n symmetric, leading dimension ld >= n; only its lower triangle
  * is read; it is not modified.  Synchronous.  Errors: CLAK_E_ARG, CLAK_E_STATE,
  * CLAK_E_EIG, CLAK_E_DEVICE. */
@@ -140,14 +140,14 @@ clak_status clak_set_kinship(clak_plan_t plan, const double* d_Phi, int64_t ld);
  * orthonormal eigenbasis gives the same results.  Synchronous. */
 clak_status clak_set_eigen(clak_plan_t plan, const double* d_Z, int64_t ldz, const double* d_w);
 
-/* Step 2 of the listing (X_L := Z^T X_L) plus the per-SNP centring basis:
- * X_L = Q_L R (FP64 Gram-Schmidt, twice), Z^T X_L and Z^T Q_L.  d_XL: n x p_L,
+/* The rotation of the covariates (X_L := Z^T X_L, section 3) plus the per-SNP
+ * centring basis: X_L = Q_L R (FP64 Gram-Schmidt, twice), Z^T X_L and Z^T Q_L.  d_XL: n x p_L,
  * leading dimension ld >= n.  Synchronous.  Errors: CLAK_E_ARG, CLAK_E_STATE,
  * CLAK_E_COV_SINGULAR (rank-deficient X_L), CLAK_E_DEVICE. */
 clak_status clak_set_covariates(clak_plan_t plan, const double* d_XL, int64_t ld);
 
-/* Step 4 (Y := Z^T Y) and the per-trait part of the loop over traits:
- * D_j = (s2_j (h2_j W + (1 - h2_j) I))^{-1}, S_TL,j = X_L^T D_j X_L (rotated
+/* The rotation of the phenotypes (Y := Z^T Y, section 3) and the per-trait
+ * part of the loop over traits: D_j = (s2_j (h2_j W + (1 - h2_j) I))^{-1}, S_TL,j = X_L^T D_j X_L (rotated
  * X_L), b_T,j, its Cholesky factor, and the per-trait operand of the grid
  * contraction.  d_Y: n x t, leading dimension ldy >= n; d_h2, d_s2: t values.
  * Synchronous.  Errors: CLAK_E_ARG (h2 outside [0,1], s2 <= 0, non-finite
@@ -155,7 +155,29 @@ clak_status clak_set_covariates(clak_plan_t plan, const double* d_XL, int64_t ld
 clak_status clak_set_traits(clak_plan_t plan, const double* d_Y, int64_t ldy,
                             const double* d_h2, const double* d_s2);
 
-/* Step 3 of the listing on one block of SNPs (X_R := Z^T X_R) and the inner
+/* Variance components of the reduced model y_j ~ N(X_L beta_j, s2_j (h2_j Phi
+ * + (1 - h2_j) I)) for every trait: the first step of the two-step analysis
+ * (section 1), by maximum likelihood or restricted maximum likelihood (the
+ * parameter estimation discussed in section 4).  beta_j and s2_j are profiled
+ * out in closed form; h2_j maximises the profile log-likelihood over [0, 1]
+ * (101 evenly spaced points, then a golden-section search on the bracket
+ * around the best of them down to a width of 1e-7).  Each evaluation costs
+ * O(n p_L^2) through the eigendecomposition of Phi (eigenvalues h2 w_k + 1 - h2).
+ *   method   : CLAK_VC_ML or CLAK_VC_REML.
+ *   d_Y      : n x t phenotypes (t of the plan), leading dimension ldy >= n.
+ *   d_h2, d_s2: t estimates each, written by the call (device memory).
+ *   d_loglik : t maximised log-likelihoods (NULL allowed).
+ * Needs set_covariates; the traits need not be set, and set traits stay valid
+ * (the call rotates d_Y into the workspace's phenotype buffer, which run_block
+ * does not read).  The outputs feed clak_set_traits directly.  Synchronous.
+ * Errors: CLAK_E_ARG (non-finite y: that trait's outputs are NaN),
+ * CLAK_E_STATE, CLAK_E_COV_SINGULAR, CLAK_E_DEVICE. */
+#define CLAK_VC_ML 0
+#define CLAK_VC_REML 1
+clak_status clak_estimate_vc(clak_plan_t plan, const double* d_Y, int64_t ldy, int method, double* d_h2,
+                             double* d_s2, double* d_loglik);
+
+/* The rotation of one block of SNPs (X_R := Z^T X_R, section 3) and the inner
  * loop over (SNP, trait) cells of that block: W_R^T W_L, W_R^T W_R, W_R^T Y_j
  * as contractions over n, then b_ij := S^{-1} b_ij.  Asynchronous.
  *   d_G     : n x m_blk genotypes (column = one SNP), element type g_dtype,

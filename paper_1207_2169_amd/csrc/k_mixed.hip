@@ -25,7 +25,7 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 
 // ------------------------------------------------------------------ rotation
 //
-// Step 3 of the multi-trait CLAK-Eig listing on one SNP block, X~ = Z^T G.
+// The SNP rotation of multi-trait CLAK-Eig (section 3) on one SNP block, X~ = Z^T G.
 // A work-group of WR x WC waves takes a BM = 32 WR (eigen rows) x BN = 32 CT
 // WC (SNPs) tile; each wave owns 32 rows x CT 32-column MFMA tiles and all four
 // digit planes of Z^T for them (v_mfma_i32_32x32x32_i8), so one genotype
