@@ -27,6 +27,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+from scipy.linalg import solve_triangular
 
 ML, REML = 0, 1
 GRID = 100
@@ -42,8 +43,8 @@ def loglik(Phi, XL, y, h2, method):
         L = np.linalg.cholesky(H)
     except np.linalg.LinAlgError:
         return -math.inf, math.nan
-    Xw = np.linalg.solve(L, XL)
-    yw = np.linalg.solve(L, y)
+    Xw = solve_triangular(L, XL, lower=True)
+    yw = solve_triangular(L, y, lower=True)
     A = Xw.T @ Xw
     beta = np.linalg.solve(A, Xw.T @ yw)
     r = yw - Xw @ beta

@@ -32,6 +32,7 @@ CLAK_VAR_MODEL, CLAK_VAR_PAPER = 0, 1
 CLAK_OUT_SNP, CLAK_OUT_FULL, CLAK_STAGE_GENOTYPES = 0, 2, 4
 CLAK_G_U8, CLAK_G_F16 = 0, 1
 CLAK_OUT_F32, CLAK_OUT_F64 = 0, 1
+CLAK_VC_ML, CLAK_VC_REML = 0, 1
 CLAK_CELL_OK, CLAK_CELL_DEGENERATE, CLAK_CELL_BAD_GENOTYPE = 0, 1, 2
 CLAK_STAGE_INGEST, CLAK_STAGE_ROTATE, CLAK_STAGE_ENCODE, CLAK_STAGE_GRID, CLAK_STAGE_COUNT = 0, 1, 2, 3, 4
 STAGE_NAMES = ("ingest", "rotate", "encode", "grid")
@@ -47,6 +48,7 @@ SIGNATURES = {
     "clak_set_eigen": (_I, [_P, _P, _I64, _P]),
     "clak_set_covariates": (_I, [_P, _P, _I64]),
     "clak_set_traits": (_I, [_P, _P, _I64, _P, _P]),
+    "clak_estimate_vc": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
     "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
     "clak_plan_destroy": (_I, [_P]),
     "clak_plan_set_profiling": (_I, [_P, _I]),
@@ -177,6 +179,24 @@ def clak_set_traits(plan: int, Y: torch.Tensor, h2: torch.Tensor, s2: torch.Tens
     h2 = _dev(h2, "h2", torch.float64).contiguous()
     s2 = _dev(s2, "s2", torch.float64).contiguous()
     _check(lib().clak_set_traits(plan, ptr, ld, h2.data_ptr(), s2.data_ptr()), "clak_set_traits")
+
+
+def clak_estimate_vc(plan: int, Y: torch.Tensor, method: int = CLAK_VC_REML, h2: Optional[torch.Tensor] = None,
+                     s2: Optional[torch.Tensor] = None, loglik: Optional[torch.Tensor] = None):
+    """Per-trait (h2, s2, loglik) of the reduced model; outputs are allocated when not given (float64, t values)."""
+    ptr, ld, _keep = _colmajor(Y, "Y")
+    t = _keep.shape[1]  # must be the plan's t
+    outs = []
+    for name, x in (("h2", h2), ("s2", s2), ("loglik", loglik)):
+        if x is None:
+            x = torch.empty(t, dtype=torch.float64, device=Y.device)
+        x = _dev(x, name, torch.float64)
+        if not x.is_contiguous() or x.numel() < t:
+            raise ValueError(f"{name}: need a contiguous float64 tensor of at least t={t} values")
+        outs.append(x)
+    _check(lib().clak_estimate_vc(plan, ptr, ld, method, outs[0].data_ptr(), outs[1].data_ptr(), outs[2].data_ptr()),
+           "clak_estimate_vc")
+    return tuple(outs)
 
 
 def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,

@@ -369,6 +369,33 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   return ok();
 }
 
+clak_status clak_estimate_vc(clak_plan_t h, const double* d_Y, int64_t ldy, int method, double* d_h2,
+                             double* d_s2, double* d_loglik) {
+  Plan* p = as_plan(h);
+  clak_status s = need_state(p, ST_COV, "estimate_vc");
+  if (s) return s;
+  if (method != CLAK_VC_ML && method != CLAK_VC_REML) return fail(CLAK_E_ARG, "estimate_vc: unknown method %d", method);
+  if (!d_Y || !d_h2 || !d_s2) return fail(CLAK_E_ARG, "estimate_vc: null Y, h2 or s2");
+  if (!device_accessible(p, d_Y) || !device_accessible(p, d_h2) || !device_accessible(p, d_s2) ||
+      (d_loglik && !device_accessible(p, d_loglik)))
+    return fail(CLAK_E_ARG, "estimate_vc: an argument is not device-accessible memory");
+  if (!aligned(d_h2, 8) || !aligned(d_s2, 8) || (d_loglik && !aligned(d_loglik, 8)))
+    return fail(CLAK_E_ARG, "estimate_vc: misaligned output");
+  if (ldy < p->n) return fail(CLAK_E_ARG, "estimate_vc: ldy=%lld < n", (long long)ldy);
+  Workspace& W = p->ws;
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(launch_rotate_real(*p, d_Y, ldy, p->t, W.Yt, p->n_pad));
+  HIP_TRY(launch_vc(*p, method, d_h2, d_s2, d_loglik));
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_TRAIT_ARG])
+    return fail(CLAK_E_ARG, "estimate_vc: %d trait(s) with non-finite values", p->hstat[DS_TRAIT_ARG]);
+  if (p->hstat[DS_TRAIT_COV])
+    return fail(CLAK_E_COV_SINGULAR, "estimate_vc: X_L^T H^-1 X_L not positive definite for %d trait(s)",
+                p->hstat[DS_TRAIT_COV]);
+  return ok();
+}
+
 }  // extern "C"
 
 namespace clak {

@@ -173,6 +173,7 @@ hipError_t launch_covariates(const Plan& p, const double* d_XL, int64_t ld);
 hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64_t ncols, double* out,
                               int64_t ldo);
 hipError_t launch_traits(const Plan& p);
+hipError_t launch_vc(const Plan& p, int method, double* h2, double* s2, double* ll);
 hipError_t launch_check_eigen(const Plan& p);
 // per block
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);

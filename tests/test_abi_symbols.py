@@ -44,4 +44,5 @@ def test_host_only_calls_without_a_gpu():
     assert lib.clak_plan_set_tuning(None, 0, 2, 64, 8) == clak.CLAK_E_ARG
     assert lib.clak_plan_get_tuning(None, None, None, None, None) == clak.CLAK_E_ARG
     assert lib.clak_autotune(None, 1, None, 0, 1, None, None, 0, 1, None, None) == clak.CLAK_E_ARG
+    assert lib.clak_estimate_vc(None, None, 1, clak.CLAK_VC_REML, None, None, None) == clak.CLAK_E_ARG
     assert b"null" in lib.clak_last_error()
