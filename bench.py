@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip clak_autotune (launch parameters timed on the first block before the timed region)")
     ap.add_argument("--tune-cache", default=None, help="clak_autotune cache file (default: none, always time)")
+    ap.add_argument("--pval", action="store_true",
+                    help="also write the two-sided Wald p-value of every cell (fused in the Schur epilogue)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="first run one plain device-to-device copy of this many bytes (reference for the "
@@ -77,24 +79,27 @@ def upload_genotypes(w, m, torch, host=False):
     return G
 
 
-def block_list(G, b, se, block):
+def block_list(G, b, se, block, pv=None):
     m = G.shape[0]
-    return [(G[s0:s0 + block], b[:, s0:s0 + block], se[:, s0:s0 + block]) for s0 in range(0, m, block)]
+    if pv is None:
+        return [(G[s0:s0 + block], b[:, s0:s0 + block], se[:, s0:s0 + block]) for s0 in range(0, m, block)]
+    return [(G[s0:s0 + block], b[:, s0:s0 + block], se[:, s0:s0 + block], None, pv[:, s0:s0 + block])
+            for s0 in range(0, m, block)]
 
 
 class Pass:
     """One step: every block of the workload, through the two-stream pipeline
     (ingest of block b+1 overlapped with block b) or per-block calls."""
 
-    def __init__(self, clak, plan, G, b, se, block, eager):
+    def __init__(self, clak, plan, G, b, se, block, eager, pv=None):
         self.clak, self.plan, self.eager = clak, plan, eager
-        self.blocks = block_list(G, b, se, block)
+        self.blocks = block_list(G, b, se, block, pv)
         self.pipe = None if eager else clak.clak_pipeline_create(plan.handle, self.blocks)
 
     def __call__(self):
         if self.pipe is None:
-            for Gb, bb, sb in self.blocks:
-                self.clak.clak_run_block(self.plan.handle, Gb, bb, sb)
+            for blk in self.blocks:
+                self.clak.clak_run_block(self.plan.handle, *blk)
         else:
             self.clak.clak_pipeline_launch(self.pipe)
 
@@ -126,7 +131,7 @@ def make_plan(clak, torch, w, block, precision, flags=0):
     return plan, t
 
 
-def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager):
+def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=None):
     """(ms per step over the timed steps, per-stage kernel times).
 
     The step time comes from HIP events around `steps` passes (pipeline
@@ -136,7 +141,7 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager):
     events add a few microseconds between launches, so the step time is
     taken from a first timed region without it and the stage times from a
     second, profiled one of the same length)."""
-    run = Pass(clak, plan, G, b, se, block, eager)
+    run = Pass(clak, plan, G, b, se, block, eager, pv)
     try:
         for _ in range(warmup):
             run()
@@ -262,6 +267,7 @@ def main():
     G = upload_genotypes(w, m, torch, host=args.host_genotypes)
     b = torch.empty((w.t, m), dtype=torch.float32, device="cuda")
     se = torch.empty_like(b)
+    pv = torch.empty_like(b) if args.pval else None
     log(f"[bench] n={w.n} p_L={w.pL} m={m} t={w.t} block={block} precision={args.precision}"
         + (" genotypes in pinned host memory" if args.host_genotypes else ""))
 
@@ -274,7 +280,7 @@ def main():
         setup["autotune_ms"] = (time.perf_counter() - t0) * 1e3
         tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
         log(f"[bench] tuned launch parameters {tuning}")
-    ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager)
+    ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager, pv)
     cells = m * w.t
     log(f"[bench] {ms:.3f} ms/step, {cells / ms * 1e3:.4e} cells/s; stages {prof}")
 
@@ -308,7 +314,8 @@ def main():
         "data": "synthetic (seeded generators; genotypes " + ("in pinned host memory, copied block by block over "
                 "PCIe by the copy engine on the ingest stream)" if args.host_genotypes else "resident in HBM)"),
         "config": {"workload": wname, "n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": m, "t": w.t, "block": block,
-                   "precision": args.precision, "parallelism": "single GPU", "tuning": tuning},
+                   "precision": args.precision, "parallelism": "single GPU", "tuning": tuning,
+                   "outputs": "b, SE, p-value" if args.pval else "b, SE"},
         "roofline": roof,
         "stage_ms_per_step": {k: v[0] for k, v in prof.items()},
         "launch": "per-block clak_run_block calls, one stream" if args.eager else
@@ -322,7 +329,8 @@ def main():
         plan.close()
         torch.cuda.empty_cache()
         p64, _ = make_plan(clak, torch, w, block, "fp64")
-        ms64, prof64 = timed_steps(clak, torch, p64, G, b, se, block, max(1, min(args.steps, 3)), 1, args.eager)
+        ms64, prof64 = timed_steps(clak, torch, p64, G, b, se, block, max(1, min(args.steps, 3)), 1, args.eager,
+                                   pv)
         p64.close()
         out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
                              "stage_ms_per_step": {k: v[0] for k, v in prof64.items()}}

@@ -179,19 +179,26 @@ clak_status clak_estimate_vc(clak_plan_t plan, const double* d_Y, int64_t ldy, i
 
 /* The rotation of one block of SNPs (X_R := Z^T X_R, section 3) and the inner
  * loop over (SNP, trait) cells of that block: W_R^T W_L, W_R^T W_R, W_R^T Y_j
- * as contractions over n, then b_ij := S^{-1} b_ij.  Asynchronous.
+ * as contractions over n, then b_ij := S^{-1} b_ij, optionally with the
+ * p-value of the SNP effect (the estimates come with their p-values in the
+ * problem statement of section 1).  Asynchronous.
  *   d_G     : n x m_blk genotypes (column = one SNP), element type g_dtype,
  *             leading dimension ldg >= n (in elements).
  *   d_b     : SNP effects; with CLAK_OUT_SNP element (i, j) at d_b[i + j*ldo],
  *             with CLAK_OUT_FULL component c at d_b[(i + j*ldo)*p + c].
  *   d_se    : standard error of the SNP effect, element (i, j) at d_se[i + j*ldo].
- *   out_dtype: CLAK_OUT_F32 or CLAK_OUT_F64 for d_b and d_se.
+ *   out_dtype: CLAK_OUT_F32 or CLAK_OUT_F64 for d_b, d_se and d_pval.
  *   ldo     : >= m_blk.
  *   d_flags : optional (NULL allowed) per-cell flags at d_flags[i + j*ldo].
+ *   d_pval  : optional (NULL allowed) two-sided p-value of the Wald statistic
+ *             z = b_snp / SE at d_pval[i + j*ldo]: P(|N(0,1)| > |z|) =
+ *             erfc(|z| / sqrt 2), equal to the chi-square(1) tail at z^2;
+ *             computed in FP64 (F32 output underflows to 0 below about
+ *             1e-45, F64 below about 1e-308, |z| > 37.5); NaN on a flagged cell.
  * 1 <= m_blk <= max_block.  Errors: CLAK_E_ARG, CLAK_E_STATE, CLAK_E_DEVICE. */
 clak_status clak_run_block(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype,
                            int64_t ldg, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                           uint8_t* d_flags);
+                           uint8_t* d_flags, void* d_pval);
 
 /* One SNP block of a pipeline or batch: the arguments of clak_run_block. */
 typedef struct clak_block {
@@ -202,6 +209,7 @@ typedef struct clak_block {
   void* se;
   int64_t ldo;
   uint8_t* flags;   /* nullable */
+  void* pval;       /* nullable */
 } clak_block;
 
 typedef struct clak_pipeline_s* clak_pipeline_t;
@@ -262,7 +270,7 @@ clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, in
  * kernel unless CLAK_OUT_FULL with p_L > 3), the fastest kept in the plan and, when cache_path is
  * not NULL, appended to that text file ("<shape> rot_cfg=C rot_rg=R
  * grid_tt=T grid_xt=X").  The block's outputs are then computed with the
- * chosen parameters, as by clak_run_block.  Synchronous.  The FP64 path has nothing
+ * chosen parameters, as by clak_run_block (without p-values).  Synchronous.  The FP64 path has nothing
  * to tune and runs the block.  Errors: as clak_run_block, CLAK_E_DEVICE. */
 clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, const char* cache_path);

@@ -49,7 +49,7 @@ SIGNATURES = {
     "clak_set_covariates": (_I, [_P, _P, _I64]),
     "clak_set_traits": (_I, [_P, _P, _I64, _P, _P]),
     "clak_estimate_vc": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
-    "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P]),
+    "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, _P]),
     "clak_plan_destroy": (_I, [_P]),
     "clak_plan_set_profiling": (_I, [_P, _I]),
     "clak_plan_set_tuning": (_I, [_P, _I, _I, _I, _I]),
@@ -63,7 +63,7 @@ SIGNATURES = {
 class clak_block(ctypes.Structure):
     _fields_ = [("m_blk", ctypes.c_int64), ("G", ctypes.c_void_p), ("ldg", ctypes.c_int64),
                 ("b", ctypes.c_void_p), ("se", ctypes.c_void_p), ("ldo", ctypes.c_int64),
-                ("flags", ctypes.c_void_p)]
+                ("flags", ctypes.c_void_p), ("pval", ctypes.c_void_p)]
 
 
 SIGNATURES.update({
@@ -200,11 +200,11 @@ def clak_estimate_vc(plan: int, Y: torch.Tensor, method: int = CLAK_VC_REML, h2:
 
 
 def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
-                   flags: Optional[torch.Tensor] = None):
-    """G: (m_blk, ldg) uint8 or float16 SNP rows; b, se: (t, ldo[, p]) float32/64."""
-    blk, gdt, odt = _block_args(G, b, se, flags)
-    _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags),
-           "clak_run_block")
+                   flags: Optional[torch.Tensor] = None, pval: Optional[torch.Tensor] = None):
+    """G: (m_blk, ldg) uint8 or float16 SNP rows; b, se, pval: (t, ldo[, p]) float32/64."""
+    blk, gdt, odt = _block_args(G, b, se, flags, pval)
+    _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags,
+                                blk.pval), "clak_run_block")
 
 
 def clak_plan_set_tuning(plan: int, rot_cfg: int = 0, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
@@ -239,7 +239,7 @@ def clak_plan_get_profile(plan: int):
     return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
 
 
-def _block_args(G, b, se, flags=None):
+def _block_args(G, b, se, flags=None, pval=None):
     """(clak_block, g_dtype, out_dtype) for one block, with the checks of clak_run_block."""
     _dev(G, "G")
     if G.dtype == torch.uint8:
@@ -264,12 +264,18 @@ def _block_args(G, b, se, flags=None):
         if flags.shape != se.shape or flags.stride() != se.stride():
             raise ValueError("flags must match the layout of se")
         fptr = flags.data_ptr()
-    blk = clak_block(G.shape[0], G.data_ptr(), G.stride(0), b.data_ptr(), se.data_ptr(), ldo, fptr)
+    pptr = None
+    if pval is not None:
+        _dev(pval, "pval", se.dtype)
+        if pval.shape != se.shape or pval.stride() != se.stride():
+            raise ValueError("pval must match the layout of se")
+        pptr = pval.data_ptr()
+    blk = clak_block(G.shape[0], G.data_ptr(), G.stride(0), b.data_ptr(), se.data_ptr(), ldo, fptr, pptr)
     return blk, gdt, odt
 
 
 def _block_array(blocks):
-    """blocks: sequence of (G, b, se[, flags]) -> ctypes array, g_dtype, out_dtype."""
+    """blocks: sequence of (G, b, se[, flags[, pval]]) -> ctypes array, g_dtype, out_dtype."""
     items = [_block_args(*blk) for blk in blocks]
     if not items:
         raise ValueError("no blocks")

@@ -53,6 +53,17 @@ clak_status need_state(const Plan* p, int min_state, const char* what) {
 
 bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
 
+CellOut cell_out(void* b, void* se, void* pval, uint8_t* flags, int64_t ldo, int out_dtype) {
+  CellOut o;
+  o.b = b;
+  o.se = se;
+  o.pval = pval;
+  o.flags = flags;
+  o.ldo = ldo;
+  o.f64 = out_dtype == CLAK_OUT_F64;
+  return o;
+}
+
 // True when the kernels of this device may dereference ptr: device memory of
 // the plan's device, managed memory, or pinned host memory mapped at the same
 // address.  Pageable host memory (which a kernel access would fault on) and
@@ -401,7 +412,7 @@ clak_status clak_estimate_vc(clak_plan_t h, const double* d_Y, int64_t ldy, int 
 namespace clak {
 
 clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
-                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags) {
+                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags, const void* d_pval) {
   if (m_blk < 1 || m_blk > p->max_block)
     return fail(CLAK_E_ARG, "run_block: m_blk=%lld outside [1, max_block=%lld]", (long long)m_blk,
                 (long long)p->max_block);
@@ -412,10 +423,12 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
   if (ldg < p->n) return fail(CLAK_E_ARG, "run_block: ldg=%lld < n", (long long)ldg);
   if (ldo < m_blk) return fail(CLAK_E_ARG, "run_block: ldo=%lld < m_blk", (long long)ldo);
   const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
-  if (!aligned(d_b, esz) || !aligned(d_se, esz)) return fail(CLAK_E_ARG, "run_block: misaligned output");
+  if (!aligned(d_b, esz) || !aligned(d_se, esz) || !aligned(d_pval, esz))
+    return fail(CLAK_E_ARG, "run_block: misaligned output");
   if (g_dtype == CLAK_G_F16 && !aligned(d_G, 2)) return fail(CLAK_E_ARG, "run_block: misaligned F16 genotypes");
   if (!device_accessible(p, d_G)) return fail(CLAK_E_ARG, "run_block: G is not device-accessible memory");
-  if (!device_accessible(p, d_b) || !device_accessible(p, d_se) || (d_flags && !device_accessible(p, d_flags)))
+  if (!device_accessible(p, d_b) || !device_accessible(p, d_se) || (d_flags && !device_accessible(p, d_flags)) ||
+      (d_pval && !device_accessible(p, d_pval)))
     return fail(CLAK_E_ARG, "run_block: an output is not device-accessible memory");
   return CLAK_OK;
 }
@@ -423,8 +436,7 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
 // Enqueues the per-block stages on the given streams (ingest on s_in, the
 // rest on s_main; the caller orders the two) using workspace slot `slot`.
 clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
-                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b, void* d_se,
-                          int out_dtype, int64_t ldo, uint8_t* d_flags) {
+                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const CellOut& out) {
   select_slot(*p, slot);
   const hipStream_t saved = p->stream;
   auto staged = [&](int stage, auto&& launch) -> hipError_t {
@@ -463,7 +475,7 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
   if (e == hipSuccess && p->prec == CLAK_PREC_MIXED && !p->fused_t1)
     e = staged(CLAK_STAGE_ENCODE, [&] { return launch_encode(*p, m_blk); });
   if (e == hipSuccess)
-    e = staged(CLAK_STAGE_GRID, [&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); });
+    e = staged(CLAK_STAGE_GRID, [&] { return launch_grid(*p, m_blk, out); });
   p->stream = saved;
   select_slot(*p, 0);
   if (e != hipSuccess) return fail(CLAK_E_DEVICE, "run_block: launch failed: %s", hipGetErrorString(e));
@@ -475,14 +487,14 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
 extern "C" {
 
 clak_status clak_run_block(clak_plan_t h, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
-                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags) {
+                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, void* d_pval) {
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_READY, "run_block");
   if (s) return s;
-  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags);
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags, d_pval);
   if (s) return s;
-  s = enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo,
-                    d_flags);
+  s = enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg,
+                    cell_out(d_b, d_se, d_pval, d_flags, ldo, out_dtype));
   if (s) return s;
   return ok();
 }
@@ -517,10 +529,10 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_READY, "autotune");
   if (s) return s;
-  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags);
+  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags, nullptr);
   if (s) return s;
-  auto run = [&]() { return enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, d_b, d_se,
-                                          out_dtype, ldo, d_flags); };
+  const CellOut out = cell_out(d_b, d_se, nullptr, d_flags, ldo, out_dtype);
+  auto run = [&]() { return enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, out); };
   if (p->prec != CLAK_PREC_MIXED) {  // nothing to tune on the FP64 path
     s = run();
     return s ? s : ok();
@@ -597,12 +609,12 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   if (tune_grid) {
     p->grid_tt = 0;
     p->grid_xt = 0;
-    best_t = MARGIN * time_ms([&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); });
+    best_t = MARGIN * time_ms([&] { return launch_grid(*p, m_blk, out); });
     for (int tt : {32, 64})
       for (int xt : pow2) {
         p->grid_tt = tt;
         p->grid_xt = xt;
-        const float ms = time_ms([&] { return launch_grid(*p, m_blk, d_b, d_se, out_dtype, ldo, d_flags); });
+        const float ms = time_ms([&] { return launch_grid(*p, m_blk, out); });
         if (ms < best_t) best_t = ms, best_tt = tt, best_xt = xt;
       }
   }

@@ -53,6 +53,17 @@ enum DevStatus : int {
 
 // Buffers of one SNP block in flight.  The workspace holds two such slots so
 // that a pipeline can ingest block b+1 while block b is rotated.
+// Where the per-cell results of one block go: cell (i, j) at element
+// i + j * ldo (b holds p values per cell under CLAK_OUT_FULL).
+struct CellOut {
+  void* b = nullptr;
+  void* se = nullptr;
+  void* pval = nullptr;      // two-sided p-value of the Wald statistic (nullable)
+  uint8_t* flags = nullptr;  // nullable
+  int64_t ldo = 0;
+  int f64 = 0;  // element type of b, se and pval: double if set, else float
+};
+
 struct Slot {
   int8_t* Gp = nullptr;
   double* sstat = nullptr;
@@ -160,11 +171,11 @@ clak_status fail(clak_status s, const char* fmt, ...);
 clak_status ok();
 clak_status need_state(const Plan* p, int min_state, const char* what);
 bool device_accessible(const Plan* p, const void* ptr);
+CellOut cell_out(void* b, void* se, void* pval, uint8_t* flags, int64_t ldo, int out_dtype);
 clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const void* d_b,
-                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags);
+                           const void* d_se, int out_dtype, int64_t ldo, const void* d_flags, const void* d_pval);
 clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
-                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b, void* d_se,
-                          int out_dtype, int64_t ldo, uint8_t* d_flags);
+                          int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const CellOut& out);
 
 // ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
 // set-up
@@ -179,9 +190,7 @@ hipError_t launch_check_eigen(const Plan& p);
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);
 hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);
 hipError_t launch_encode(const Plan& p, int64_t m_blk);
-hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                         uint8_t* d_flags);
-hipError_t launch_grid(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                       uint8_t* d_flags);
+hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out);
+hipError_t launch_grid(const Plan& p, int64_t m_blk, const CellOut& out);
 
 }  // namespace clak

@@ -163,8 +163,7 @@ template <int PL>
 __global__ void __launch_bounds__(256) k_grid64(int64_t np, int64_t m_blk, int64_t t, const double* __restrict__ X,
                                                 const double* __restrict__ V, const double* __restrict__ Dm,
                                                 const double* __restrict__ tpar, const double* __restrict__ sstat,
-                                                uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
-                                                int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
+                                                uint32_t flags, CellOut out) {
   constexpr int NCV = 16 * (PL + 1), NC = NCV + 16, NCT = NC / 16, BK = 16;
   __shared__ double As[BK][64 + 1];
   __shared__ double Bs[BK][NC + 1];
@@ -217,24 +216,21 @@ __global__ void __launch_bounds__(256) k_grid64(int64_t np, int64_t m_blk, int64
         for (int l = 0; l < PL; ++l) c[l] = Cs[s][jj * (PL + 1) + l];
         const double r = Cs[s][jj * (PL + 1) + PL];
         const double a = Cs[s][NCV + jj];
-        schur_store<PL>(c, r, a, tpar + j * trait_stride(PL), sstat + i * snp_stride(PL), flags, i, j, ob, ose,
-                        out_f64, ldo, oflags);
+        schur_store<PL>(c, r, a, tpar + j * trait_stride(PL), sstat + i * snp_stride(PL), flags, i, j, out);
       }
     }
     __syncthreads();
   }
 }
 
-hipError_t launch_grid_fp64(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                            uint8_t* d_flags) {
-  if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
+hipError_t launch_grid_fp64(const Plan& p, int64_t m_blk, const CellOut& out) {
+  if (p.fused_t1) return launch_fin_t1(p, m_blk, out);
   dim3 grid((unsigned)((m_blk + 63) / 64), (unsigned)(p.t_pad / 16));
-  const int f64 = out_dtype == CLAK_OUT_F64;
   const Workspace& W = p.ws;
 #define CLAK_G64(PLV)                                                                                             \
   case PLV:                                                                                                       \
     k_grid64<PLV><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.t, W.X64, W.V64, W.D64, W.tpar, W.sstat, p.flags, \
-                                              d_b, d_se, f64, ldo, d_flags);                                      \
+                                              out);                                                               \
     break;
   switch (p.pL) {
     CLAK_G64(1) CLAK_G64(2) CLAK_G64(3) CLAK_G64(4) CLAK_G64(5) CLAK_G64(6) CLAK_G64(7) CLAK_G64(8)
@@ -247,17 +243,14 @@ hipError_t launch_grid_fp64(const Plan& p, int64_t m_blk, void* d_b, void* d_se,
 }
 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk);
-hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                             uint8_t* d_flags);
+hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, const CellOut& out);
 
 hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk) {
   return p.prec == CLAK_PREC_MIXED ? launch_rotate_snps_mixed(p, m_blk) : launch_rotate_snps_fp64(p, m_blk);
 }
 
-hipError_t launch_grid(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                       uint8_t* d_flags) {
-  return p.prec == CLAK_PREC_MIXED ? launch_grid_mixed(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags)
-                                   : launch_grid_fp64(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
+hipError_t launch_grid(const Plan& p, int64_t m_blk, const CellOut& out) {
+  return p.prec == CLAK_PREC_MIXED ? launch_grid_mixed(p, m_blk, out) : launch_grid_fp64(p, m_blk, out);
 }
 
 }  // namespace clak

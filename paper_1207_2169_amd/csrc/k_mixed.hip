@@ -256,9 +256,7 @@ static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0, "rotation tiles must div
 template <int PL>
 __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp,
                                                 const double* __restrict__ part, const double* __restrict__ tpar,
-                                                const double* __restrict__ sstat, uint32_t flags,
-                                                void* __restrict__ ob, void* __restrict__ ose, int out_f64,
-                                                int64_t ldo, uint8_t* __restrict__ oflags) {
+                                                const double* __restrict__ sstat, uint32_t flags, CellOut out) {
   constexpr int NP = PL + 2;
   __shared__ double red[4][64][NP + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -277,8 +275,7 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
   if (wid != 0 || i >= m_blk) return;
 #pragma unroll
   for (int q = 0; q < NP; ++q) s[q] = ((red[0][lane][q] + red[1][lane][q]) + red[2][lane][q]) + red[3][lane][q];
-  schur_store<PL>(s, s[PL], s[PL + 1], tpar, sstat + i * snp_stride(PL), flags, i, 0, ob, ose, out_f64, ldo,
-                  oflags);
+  schur_store<PL>(s, s[PL], s[PL + 1], tpar, sstat + i * snp_stride(PL), flags, i, 0, out);
 }
 
 // Digit encoding of the rotated SNPs for the grid contraction: x with scale
@@ -381,8 +378,7 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
                                                  int64_t vplane, const int8_t* __restrict__ Dd, int64_t dplane,
                                                  const double* __restrict__ vs, const double* __restrict__ ds,
                                                  const double* __restrict__ tpar, const double* __restrict__ sstat,
-                                                 uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
-                                                 int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
+                                                 uint32_t flags, CellOut out) {
   constexpr int NCV = 16 * (PL + 1), NC = NCV + 16, NCT = NC / 16, BK = 64;
   constexpr int A_BYTES = 8 * 64 * LROW, B_BYTES = 4 * NC * LROW;
   constexpr int C_BYTES = 16 * (NC + 1) * 8;
@@ -471,8 +467,7 @@ __global__ void __launch_bounds__(256) k_grid_i8(int64_t np, int64_t m_blk, int6
         for (int l = 0; l < PL; ++l) c[l] = Cs[s][jj * (PL + 1) + l];
         const double r = Cs[s][jj * (PL + 1) + PL];
         const double a = Cs[s][NCV + jj];
-        schur_store<PL>(c, r, a, tpar + j * trait_stride(PL), sstat + i * ss, flags, i, j, ob, ose, out_f64, ldo,
-                        oflags);
+        schur_store<PL>(c, r, a, tpar + j * trait_stride(PL), sstat + i * ss, flags, i, j, out);
       }
     }
     __syncthreads();
@@ -575,8 +570,7 @@ __global__ void __launch_bounds__(256, 1)
     k_grid32(int64_t np, int64_t m_blk, int64_t mbp, int64_t t, int64_t tp, int64_t ntn, int64_t ntt, int xt,
              const int8_t* __restrict__ Xd, const int8_t* __restrict__ Vd, const int8_t* __restrict__ Dd,
              const double* __restrict__ vs, const double* __restrict__ ds, const double* __restrict__ tpar,
-             const double* __restrict__ sstat, uint32_t flags, void* __restrict__ ob, void* __restrict__ ose,
-             int out_f64, int64_t ldo, uint8_t* __restrict__ oflags) {
+             const double* __restrict__ sstat, uint32_t flags, CellOut out) {
   constexpr int NV = PL + 1, NG = TT / 32, NH = (NV + 3) / 4;  // NH chunks of at most four entries
   static_assert(NG <= 4 && NH <= 3, "at most four accumulator tiles per wave, p_L <= 11");
   __shared__ __attribute__((aligned(16))) int8_t smem[2 * G32_STAGE];
@@ -654,7 +648,7 @@ __global__ void __launch_bounds__(256, 1)
             }
             if (H == NH - 1)
               schur_store_cc<PL>(ccp[r], rr, araw[g][r] * sd * gx * gx, tpar + j * trait_stride(PL), st, flags, i,
-                                 j, ob, ose, out_f64, ldo, oflags);
+                                 j, out);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -680,7 +674,7 @@ __global__ void __launch_bounds__(256, 1)
           double v[NV];
 #pragma unroll
           for (int q = 0; q < NV; ++q) v[q] = g32_value(acc[q], r) * sc[q] * gx;
-          schur_store<PL>(v, v[PL], araw[g][r] * sd * gx * gx, tpj, st, flags, i, j, ob, ose, out_f64, ldo, oflags);
+          schur_store<PL>(v, v[PL], araw[g][r] * sd * gx * gx, tpj, st, flags, i, j, out);
         }
         __builtin_amdgcn_sched_barrier(0);  // one cell at a time: keeps the accumulator reads from being hoisted
       }
@@ -688,16 +682,13 @@ __global__ void __launch_bounds__(256, 1)
   }
 }
 
-hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                         uint8_t* d_flags) {
-  const int f64 = out_dtype == CLAK_OUT_F64;
+hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out) {
   const Workspace& W = p.ws;
   dim3 fgrid((unsigned)((m_blk + 63) / 64));
   const int64_t nrt = p.prec == CLAK_PREC_MIXED ? p.n_pad / ROT_BM : p.n_pad / 64;
 #define CLAK_F1(PLV)                                                                                          \
   case PLV:                                                                                                   \
-    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags,          \
-                                               d_b, d_se, f64, ldo, d_flags);                                 \
+    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
     break;
   switch (p.pL) {
     CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)
@@ -709,11 +700,9 @@ hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, void* d_b, void* d_se, in
   return hipGetLastError();
 }
 
-hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se, int out_dtype, int64_t ldo,
-                             uint8_t* d_flags) {
-  const int f64 = out_dtype == CLAK_OUT_F64;
+hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, const CellOut& out) {
   const Workspace& W = p.ws;
-  if (p.fused_t1) return launch_fin_t1(p, m_blk, d_b, d_se, out_dtype, ldo, d_flags);
+  if (p.fused_t1) return launch_fin_t1(p, m_blk, out);
   if (p.pL <= 3 || !(p.flags & CLAK_OUT_FULL)) {
     // traits per work-group: 64 unless 32 gives fewer modelled
     // dispatch rounds of 256 work-groups x traits per tile
@@ -732,8 +721,7 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
     const dim3 g32((unsigned)(8 * gt * gs));
 #define CLAK_G32(PLV, TTV)                                                                                       \
   k_grid32<PLV, TTV><<<g32, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, p.t, p.t_pad, ntn, ntt, xt, W.Xd, W.Vd, \
-                                                W.Dd, W.vs, W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, ldo,  \
-                                                d_flags)
+                                                W.Dd, W.vs, W.ds, W.tpar, W.sstat, p.flags, out)
 #define CLAK_G32T(PLV)   \
   case PLV:              \
     if (tt == 32)        \
@@ -755,8 +743,7 @@ hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, void* d_b, void* d_se
 #define CLAK_GI8(PLV)                                                                                              \
   case PLV:                                                                                                        \
     k_grid_i8<PLV><<<grid, 256, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, p.t, p.t_pad, W.Xd, xplane, W.Vd, vplane, \
-                                               W.Dd, dplane, W.vs, W.ds, W.tpar, W.sstat, p.flags, d_b, d_se, f64, \
-                                               ldo, d_flags);                                                      \
+                                               W.Dd, dplane, W.vs, W.ds, W.tpar, W.sstat, p.flags, out);           \
     break;
   switch (p.pL) {
     CLAK_GI8(4) CLAK_GI8(5) CLAK_GI8(6) CLAK_GI8(7) CLAK_GI8(8)

@@ -94,7 +94,7 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
       if (j >= NSLOTS) CK(hipStreamWaitEvent(c.s_in, c.done[slot], 0), what);
       const clak_block& B = g->blocks[c.first + j];
       clak_status st = enqueue_block(p, slot, c.s_in, c.s_main, c.ingested[slot], B.m_blk, B.G, g->g_dtype, B.ldg,
-                                     B.b, B.se, g->out_dtype, B.ldo, B.flags);
+                                     cell_out(B.b, B.se, B.pval, B.flags, B.ldo, g->out_dtype));
       if (st) return st;
       CK(hipEventRecord(c.done[slot], c.s_main), what);
     }
@@ -109,7 +109,7 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
 clak_status check_blocks(Plan* p, int64_t n, const clak_block* blocks, int g_dtype, int out_dtype) {
   for (int64_t b = 0; b < n; ++b) {
     const clak_block& B = blocks[b];
-    clak_status s = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags);
+    clak_status s = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval);
     if (s) return s;
   }
   return CLAK_OK;

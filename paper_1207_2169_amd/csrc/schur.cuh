@@ -8,17 +8,39 @@
 //   s  = a - ||c'||^2        (Schur complement, = 1 / [S^{-1}]_pp)
 //   b_snp = r' / s,  Var(b_snp) = 1 / s  (times s2_j under CLAK_VAR_PAPER)
 //   b_cov = u - L^{-T} c' b_snp - gamma b_snp   (gamma undoes the centring)
+//   z = b_snp / SE, p = erfc(|z| / sqrt 2)     (optional)
 #pragma once
 
 #include "common.cuh"
 
 namespace clak {
 
+// The SNP-effect outputs of one cell: b_snp, SE, the two-sided p-value of the
+// Wald statistic z = b_snp / SE (P(|N(0,1)| > |z|) = erfc(|z| / sqrt 2), the
+// upper tail of chi-square with one degree of freedom at z^2), and the flag.
+__device__ __forceinline__ void store_snp(const CellOut& out, int64_t o, double bsnp, double se, int flag,
+                                          bool write_b) {
+  if (out.f64) {
+    if (write_b) ((double*)out.b)[o] = bsnp;
+    ((double*)out.se)[o] = se;
+  } else {
+    if (write_b) ((float*)out.b)[o] = (float)bsnp;
+    ((float*)out.se)[o] = (float)se;
+  }
+  if (out.pval) {
+    const double pv = flag ? __builtin_nan("") : erfc(fabs(bsnp / se) * M_SQRT1_2);
+    if (out.f64)
+      ((double*)out.pval)[o] = pv;
+    else
+      ((float*)out.pval)[o] = (float)pv;
+  }
+  if (out.flags) out.flags[o] = (uint8_t)flag;
+}
+
 template <int PL>
 __device__ __forceinline__ void schur_store(const double* c, double r, double a, const double* __restrict__ tp,
                                             const double* __restrict__ st, uint32_t flags, int64_t i, int64_t j,
-                                            void* __restrict__ ob, void* __restrict__ ose, int out_f64, int64_t ldo,
-                                            uint8_t* __restrict__ oflags) {
+                                            const CellOut& out) {
   const double nan = __builtin_nan("");
   int flag = (int)st[2 * PL + 1];
   double cc = 0.0;
@@ -32,7 +54,7 @@ __device__ __forceinline__ void schur_store(const double* c, double r, double a,
     const double var = (flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] / s : 1.0 / s;
     se = sqrt(var);
   }
-  const int64_t o = i + j * ldo;
+  const int64_t o = i + j * out.ldo;
   if (flags & CLAK_OUT_FULL) {
     double bf[PL + 1];
 #pragma unroll
@@ -43,33 +65,23 @@ __device__ __forceinline__ void schur_store(const double* c, double r, double a,
       bf[q] = flag ? nan : tp[PL * PL + q] - (lc + st[PL + q]) * bsnp;
     }
     bf[PL] = bsnp;
-    if (out_f64) {
+    if (out.f64) {
 #pragma unroll
-      for (int q = 0; q <= PL; ++q) ((double*)ob)[o * (PL + 1) + q] = bf[q];
+      for (int q = 0; q <= PL; ++q) ((double*)out.b)[o * (PL + 1) + q] = bf[q];
     } else {
 #pragma unroll
-      for (int q = 0; q <= PL; ++q) ((float*)ob)[o * (PL + 1) + q] = (float)bf[q];
+      for (int q = 0; q <= PL; ++q) ((float*)out.b)[o * (PL + 1) + q] = (float)bf[q];
     }
-  } else {
-    if (out_f64)
-      ((double*)ob)[o] = bsnp;
-    else
-      ((float*)ob)[o] = (float)bsnp;
   }
-  if (out_f64)
-    ((double*)ose)[o] = se;
-  else
-    ((float*)ose)[o] = (float)se;
-  if (oflags) oflags[o] = (uint8_t)flag;
+  store_snp(out, o, bsnp, se, flag, !(flags & CLAK_OUT_FULL));
 }
 
 // The SNP-effect form of schur_store when ||c'||^2 has been accumulated in
-// pieces (cc): b_snp, SE and the flag of the cell.
+// pieces (cc).
 template <int PL>
 __device__ __forceinline__ void schur_store_cc(double cc, double r, double a, const double* __restrict__ tp,
                                                const double* __restrict__ st, uint32_t flags, int64_t i, int64_t j,
-                                               void* __restrict__ ob, void* __restrict__ ose, int out_f64,
-                                               int64_t ldo, uint8_t* __restrict__ oflags) {
+                                               const CellOut& out) {
   int flag = (int)st[2 * PL + 1];
   const double s = a - cc;
   if (flag == 0 && !(s > 1e-10 * a)) flag = CLAK_CELL_DEGENERATE;
@@ -78,15 +90,7 @@ __device__ __forceinline__ void schur_store_cc(double cc, double r, double a, co
     bsnp = r / s;
     se = sqrt((flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] / s : 1.0 / s);
   }
-  const int64_t o = i + j * ldo;
-  if (out_f64) {
-    ((double*)ob)[o] = bsnp;
-    ((double*)ose)[o] = se;
-  } else {
-    ((float*)ob)[o] = (float)bsnp;
-    ((float*)ose)[o] = (float)se;
-  }
-  if (oflags) oflags[o] = (uint8_t)flag;
+  store_snp(out, i + j * out.ldo, bsnp, se, flag, true);
 }
 
 }  // namespace clak

@@ -8,10 +8,11 @@ import oracle
 
 
 def gpu_run(w, precision, flags=0, block=None, g_dtype="u8", out_dtype="f64", ldg_pad=0, ldo_pad=0,
-            snp_range=None, eigen=None, want_flags=True):
+            snp_range=None, eigen=None, want_flags=True, want_pval=False):
     """b, se, cell flags of every cell in SNPs [start, stop) of workload w.
 
-    Returns b (m, t) or (m, t, p) with CLAK_OUT_FULL, se (m, t), flags (m, t)."""
+    Returns b (m, t) or (m, t, p) with CLAK_OUT_FULL, se (m, t), flags (m, t),
+    and with want_pval the p-values (m, t) as a fourth item."""
     import torch
 
     from paper_1207_2169_amd import clak
@@ -34,7 +35,7 @@ def gpu_run(w, precision, flags=0, block=None, g_dtype="u8", out_dtype="f64", ld
         Y = torch.from_numpy(np.ascontiguousarray(w.Y.T)).to(dev).t()
         clak.clak_set_traits(plan.handle, Y, torch.from_numpy(w.h2).to(dev), torch.from_numpy(w.s2).to(dev))
         full = bool(flags & clak.CLAK_OUT_FULL)
-        bs, ses, fls = [], [], []
+        bs, ses, fls, pvs = [], [], [], []
         for s0 in range(start, stop, block):
             mb = min(block, stop - s0)
             g = w.genotypes(s0, mb, ld=w.n + ldg_pad)
@@ -45,7 +46,8 @@ def gpu_run(w, precision, flags=0, block=None, g_dtype="u8", out_dtype="f64", ld
             b = torch.full((w.t, ldo, p) if full else (w.t, ldo), float("inf"), dtype=odt, device=dev)
             se = torch.full((w.t, ldo), float("inf"), dtype=odt, device=dev)
             fl = torch.full((w.t, ldo), 255, dtype=torch.uint8, device=dev) if want_flags else None
-            clak.clak_run_block(plan.handle, G, b, se, fl)
+            pv = torch.full((w.t, ldo), float("inf"), dtype=odt, device=dev) if want_pval else None
+            clak.clak_run_block(plan.handle, G, b, se, fl, pv)
             torch.cuda.synchronize()
             if ldo_pad:
                 assert torch.isinf(se[:, mb:]).all(), "output padding overwritten"
@@ -53,10 +55,16 @@ def gpu_run(w, precision, flags=0, block=None, g_dtype="u8", out_dtype="f64", ld
             ses.append(se[:, :mb].cpu().numpy().astype(np.float64))
             if want_flags:
                 fls.append(fl[:, :mb].cpu().numpy())
+            if want_pval:
+                if ldo_pad:
+                    assert torch.isinf(pv[:, mb:]).all(), "p-value padding overwritten"
+                pvs.append(pv[:, :mb].cpu().numpy().astype(np.float64))
         b = np.concatenate(bs, axis=1)
         se = np.concatenate(ses, axis=1)
         fl = np.concatenate(fls, axis=1) if want_flags else None
     b = np.moveaxis(b, 0, 1)  # (m, t[, p])
+    if want_pval:
+        return b, se.T, (fl.T if fl is not None else None), np.concatenate(pvs, axis=1).T
     return b, se.T, (fl.T if fl is not None else None)
 
 

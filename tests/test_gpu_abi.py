@@ -171,7 +171,7 @@ def test_pinned_host_genotypes_and_pageable_refusal():
         b, se = outs[0]
         st = clak.lib().clak_run_block(plan.handle, w.m, ctypes.c_void_p(g.data_ptr()), clak.CLAK_G_U8, w.n,
                                        ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(se.data_ptr()),
-                                       clak.CLAK_OUT_F64, w.m, None)
+                                       clak.CLAK_OUT_F64, w.m, None, None)
         assert st == clak.CLAK_E_ARG
         assert b"device-accessible" in clak.lib().clak_last_error()
     # with CLAK_STAGE_GENOTYPES every block goes through the copy engine into a staging buffer
