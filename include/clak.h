@@ -89,6 +89,15 @@ typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_pre
                                    16-byte-aligned rows, then ingested.  Without the
                                    flag the ingest kernel reads the caller's block,
                                    also a pinned host block over PCIe.            */
+#define CLAK_CHOL 8u        /* single trait (t = 1) by CLAK-Chol (section 2): no
+                               eigendecomposition.  clak_set_kinship keeps Phi;
+                               clak_set_traits factors H = h2 Phi + (1 - h2) I =
+                               U^T U (FP64 Cholesky) and rotates by U^-T, a lower-
+                               triangular matrix, in place of Z^T, with unit
+                               weights (M^-1 = U^-1 U^-T / s2), so the SNP rotation
+                               skips the zero half of the matrix.  clak_set_eigen
+                               and clak_estimate_vc need eigenpairs and return
+                               CLAK_E_UNSUPPORTED for such a plan.              */
 
 /* Genotype element types accepted by clak_run_block (values 0, 1, 2). */
 #define CLAK_G_U8 0

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "CLAK_OK", 1: "CLAK_E_ARG", 2: "CLAK_E_STATE", 3: "CLAK_E_NOT
                 8: "CLAK_E_UNSUPPORTED"}
 CLAK_PREC_FP64, CLAK_PREC_MIXED = 0, 1
 CLAK_VAR_MODEL, CLAK_VAR_PAPER = 0, 1
-CLAK_OUT_SNP, CLAK_OUT_FULL, CLAK_STAGE_GENOTYPES = 0, 2, 4
+CLAK_OUT_SNP, CLAK_OUT_FULL, CLAK_STAGE_GENOTYPES, CLAK_CHOL = 0, 2, 4, 8
 CLAK_G_U8, CLAK_G_F16 = 0, 1
 CLAK_OUT_F32, CLAK_OUT_F64 = 0, 1
 CLAK_VC_ML, CLAK_VC_REML = 0, 1

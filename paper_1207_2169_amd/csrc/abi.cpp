@@ -139,6 +139,10 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   W.Qt = (double*)take(8 * np * pl);
   W.Yt = (double*)take(8 * np * p.t);
   W.tpar = (double*)take(8 * tp * trait_stride(p.pL));
+  if (p.flags & CLAK_CHOL) {
+    W.Phi = (double*)take(8 * np * np);
+    W.XL = (double*)take(8 * np * pl);
+  }
   if (p.prec == CLAK_PREC_FP64 || p.fused_t1) {
     W.V64 = (double*)take(8 * tp * (pl + 1) * np);
     W.D64 = (double*)take(8 * tp * np);
@@ -193,8 +197,9 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   if (max_block < 1) return fail(CLAK_E_ARG, "plan_create: max_block must be >= 1");
   if (precision != CLAK_PREC_FP64 && precision != CLAK_PREC_MIXED)
     return fail(CLAK_E_ARG, "plan_create: unknown precision %d", precision);
-  if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL | CLAK_STAGE_GENOTYPES))
+  if (flags & ~(CLAK_VAR_PAPER | CLAK_OUT_FULL | CLAK_STAGE_GENOTYPES | CLAK_CHOL))
     return fail(CLAK_E_ARG, "plan_create: unknown flags 0x%x", flags);
+  if ((flags & CLAK_CHOL) && t != 1) return fail(CLAK_E_ARG, "plan_create: CLAK_CHOL needs t = 1");
   if (precision == CLAK_PREC_MIXED && p_L > 8)
     return fail(CLAK_E_UNSUPPORTED, "plan_create: mixed precision supports p_L <= 8");
   if (precision == CLAK_PREC_MIXED && n > MIXED_MAX_N)
@@ -266,6 +271,43 @@ clak_status clak_plan_set_stream(clak_plan_t h, void* stream) {
   return ok();
 }
 
+// CLAK-Chol set-up of one trait: H = h2 Phi + (1 - h2) I = U^T U, U^-1 in
+// place, rotation rows U^-T with unit weights, then the rotations of X_L and
+// Q_L by it (what set_kinship and set_covariates do for CLAK-Eig).
+static clak_status chol_factor(Plan* p, const double* d_h2) {
+  Workspace& W = p->ws;
+  const int64_t n = p->n, np = p->n_pad;
+  HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+  HIP_TRY(launch_chol_build(*p, d_h2));
+  clak_status s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_TRAIT_ARG]) return fail(CLAK_E_ARG, "set_traits: h2 outside [0,1]");
+  rocblas_handle rb = (rocblas_handle)p->rocblas;
+  if (rocblas_set_stream(rb, p->stream) != rocblas_status_success)
+    return fail(CLAK_E_DEVICE, "set_traits: rocblas_set_stream failed");
+  rocblas_status rs = rocsolver_dpotrf(rb, rocblas_fill_upper, (rocblas_int)n, W.Zt, (rocblas_int)np,
+                                       W.dstat + DS_EIG_INFO);
+  if (rs != rocblas_status_success) return fail(CLAK_E_DEVICE, "set_traits: rocsolver_dpotrf status %d", (int)rs);
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_EIG_INFO] != 0)
+    return fail(CLAK_E_NOT_SPD, "set_traits: h2 Phi + (1 - h2) I is not positive definite (pivot %d)",
+                p->hstat[DS_EIG_INFO]);
+  rs = rocsolver_dtrtri(rb, rocblas_fill_upper, rocblas_diagonal_non_unit, (rocblas_int)n, W.Zt, (rocblas_int)np,
+                        W.dstat + DS_EIG_INFO);
+  if (rs != rocblas_status_success) return fail(CLAK_E_DEVICE, "set_traits: rocsolver_dtrtri status %d", (int)rs);
+  HIP_TRY(launch_chol_fix(*p));
+  HIP_TRY(launch_check_eigen(*p));
+  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p));
+  HIP_TRY(launch_rotate_real(*p, W.XL, np, p->pL, W.XLt, np));
+  HIP_TRY(launch_rotate_real(*p, W.QL, np, p->pL, W.Qt, np));
+  s = sync_and_read_status(p);
+  if (s) return s;
+  if (p->hstat[DS_EIG_INFO] != 0) return fail(CLAK_E_NOT_SPD, "set_traits: singular Cholesky factor");
+  if (p->hstat[DS_EIGVAL]) return fail(CLAK_E_ARG, "set_traits: non-finite inverse Cholesky factor");
+  return CLAK_OK;
+}
+
 static clak_status finish_eigen(Plan* p) {
   // zero the status words, validate the eigenpairs, split Z^T into digits
   HIP_TRY(launch_check_eigen(*p));
@@ -287,6 +329,18 @@ clak_status clak_set_kinship(clak_plan_t h, const double* d_Phi, int64_t ld) {
   p->state = ST_WS;
   const int64_t n = p->n, np = p->n_pad;
   Workspace& W = p->ws;
+  if (p->flags & CLAK_CHOL) {
+    // CLAK-Chol: keep Phi; the factorisation needs h2 and happens in set_traits
+    HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
+    HIP_TRY(hipMemcpy2DAsync(W.Phi, sizeof(double) * np, d_Phi, sizeof(double) * ld, sizeof(double) * n, n,
+                             hipMemcpyDeviceToDevice, p->stream));
+    HIP_TRY(launch_chol_check(*p));
+    s = sync_and_read_status(p);
+    if (s) return s;
+    if (p->hstat[DS_EIGVAL]) return fail(CLAK_E_ARG, "set_kinship: non-finite Phi");
+    p->state = ST_EIG;
+    return ok();
+  }
   HIP_TRY(hipMemsetAsync(W.Zt, 0, sizeof(double) * np * np, p->stream));
   HIP_TRY(hipMemsetAsync(W.w, 0, sizeof(double) * np, p->stream));
   HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
@@ -309,6 +363,7 @@ clak_status clak_set_eigen(clak_plan_t h, const double* d_Z, int64_t ldz, const 
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_WS, "set_eigen");
   if (s) return s;
+  if (p->flags & CLAK_CHOL) return fail(CLAK_E_UNSUPPORTED, "set_eigen: a CLAK_CHOL plan takes Phi (set_kinship)");
   if (!d_Z || !d_w) return fail(CLAK_E_ARG, "set_eigen: null Z or w");
   if (!device_accessible(p, d_Z) || !device_accessible(p, d_w))
     return fail(CLAK_E_ARG, "set_eigen: Z or w is not device-accessible memory");
@@ -336,8 +391,15 @@ clak_status clak_set_covariates(clak_plan_t h, const double* d_XL, int64_t ld) {
   Workspace& W = p->ws;
   HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
   HIP_TRY(launch_covariates(*p, d_XL, ld));
-  HIP_TRY(launch_rotate_real(*p, d_XL, ld, p->pL, W.XLt, p->n_pad));
-  HIP_TRY(launch_rotate_real(*p, W.QL, p->n_pad, p->pL, W.Qt, p->n_pad));
+  if (p->flags & CLAK_CHOL) {
+    // the rotation depends on h2: X_L is kept and rotated in set_traits
+    HIP_TRY(hipMemsetAsync(W.XL, 0, sizeof(double) * p->n_pad * p->pL, p->stream));
+    HIP_TRY(hipMemcpy2DAsync(W.XL, sizeof(double) * p->n_pad, d_XL, sizeof(double) * ld, sizeof(double) * p->n,
+                             p->pL, hipMemcpyDeviceToDevice, p->stream));
+  } else {
+    HIP_TRY(launch_rotate_real(*p, d_XL, ld, p->pL, W.XLt, p->n_pad));
+    HIP_TRY(launch_rotate_real(*p, W.QL, p->n_pad, p->pL, W.Qt, p->n_pad));
+  }
   s = sync_and_read_status(p);
   if (s) return s;
   if (p->hstat[DS_COV] == 1) return fail(CLAK_E_ARG, "set_covariates: non-finite X_L");
@@ -357,6 +419,10 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   if (ldy < p->n) return fail(CLAK_E_ARG, "set_traits: ldy=%lld < n", (long long)ldy);
   p->state = ST_COV;
   Workspace& W = p->ws;
+  if (p->flags & CLAK_CHOL) {
+    s = chol_factor(p, d_h2);
+    if (s) return s;
+  }
   HIP_TRY(hipMemsetAsync(W.dstat, 0, sizeof(int) * DS_COUNT, p->stream));
   HIP_TRY(launch_rotate_real(*p, d_Y, ldy, p->t, W.Yt, p->n_pad));
   // per-trait h2 and s2 travel through the parameter block (slot pL*pL+pL: s2, +1: h2)
@@ -385,6 +451,8 @@ clak_status clak_estimate_vc(clak_plan_t h, const double* d_Y, int64_t ldy, int 
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_COV, "estimate_vc");
   if (s) return s;
+  if (p->flags & CLAK_CHOL)
+    return fail(CLAK_E_UNSUPPORTED, "estimate_vc: needs the eigenvalues of Phi (not a CLAK_CHOL plan)");
   if (method != CLAK_VC_ML && method != CLAK_VC_REML) return fail(CLAK_E_ARG, "estimate_vc: unknown method %d", method);
   if (!d_Y || !d_h2 || !d_s2) return fail(CLAK_E_ARG, "estimate_vc: null Y, h2 or s2");
   if (!device_accessible(p, d_Y) || !device_accessible(p, d_h2) || !device_accessible(p, d_s2) ||

@@ -91,6 +91,8 @@ struct Workspace {
   double* XLt = nullptr;    // n_pad x pL column-major: Z^T X_L
   double* Qt = nullptr;     // n_pad x pL column-major: Z^T Q_L
   double* Yt = nullptr;     // n_pad x t  column-major: Z^T Y
+  double* Phi = nullptr;    // CLAK_CHOL: n_pad x n_pad copy of Phi (lower triangle used)
+  double* XL = nullptr;     // CLAK_CHOL: n_pad x pL copy of X_L (rotated at set_traits)
   double* tpar = nullptr;   // t_pad x trait_stride
   // per block (the slot selected for the block being launched)
   int8_t* Gp = nullptr;     // mb_pad SNP rows x n_pad individuals, K-tiled (kt32), zero padded
@@ -186,6 +188,9 @@ hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64
 hipError_t launch_traits(const Plan& p);
 hipError_t launch_vc(const Plan& p, int method, double* h2, double* s2, double* ll);
 hipError_t launch_check_eigen(const Plan& p);
+hipError_t launch_chol_check(const Plan& p);
+hipError_t launch_chol_build(const Plan& p, const double* d_h2);
+hipError_t launch_chol_fix(const Plan& p);
 // per block
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);
 hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);

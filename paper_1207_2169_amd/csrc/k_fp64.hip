@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_rot64(int64_t n, int64_t np, int pL, co
                                                double* __restrict__ out, int64_t ldo, const double* __restrict__ Qt,
                                                const double* __restrict__ sstat, const double* __restrict__ V,
                                                const double* __restrict__ Dv, double* __restrict__ part,
-                                               int64_t mbp) {
+                                               int64_t mbp, int tri) {
   constexpr int BM = 64, BN = 64, BK = 16, NPM = MAX_PL + 2;
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
@@ -40,7 +40,8 @@ __global__ void __launch_bounds__(256) k_rot64(int64_t n, int64_t np, int pL, co
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = (v4d){0.0, 0.0, 0.0, 0.0};
   const int lr = tid >> 2, lk = (tid & 3) * 4;
-  for (int64_t k0 = 0; k0 < np; k0 += BK) {
+  const int64_t kend = tri ? min(np, m0 + BM) : np;  // lower-triangular Z^T: K tiles up to the diagonal
+  for (int64_t k0 = 0; k0 < kend; k0 += BK) {
     {
       const double* src = Zt + (m0 + lr) * np + k0 + lk;
 #pragma unroll
@@ -138,7 +139,7 @@ hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64
                               int64_t ldo) {
   dim3 grid((unsigned)(p.n_pad / 64), (unsigned)((ncols + 63) / 64));
   k_rot64<0><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, p.ws.Zt, B, ldb, ncols, out, ldo, nullptr,
-                                         nullptr, nullptr, nullptr, nullptr, 0);
+                                         nullptr, nullptr, nullptr, nullptr, 0, (p.flags & CLAK_CHOL) ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -146,12 +147,13 @@ hipError_t launch_rotate_snps_fp64(const Plan& p, int64_t m_blk) {
   const int64_t m_pad = roundup(m_blk, 64);
   dim3 grid((unsigned)(p.n_pad / 64), (unsigned)(m_pad / 64));
   const Workspace& W = p.ws;
+  const int tri = (p.flags & CLAK_CHOL) ? 1 : 0;
   if (p.fused_t1)
     k_rot64<2><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.mb_pad, m_pad, nullptr, 0, W.Qt,
-                                           W.sstat, W.V64, W.D64, W.part, p.mb_pad);
+                                           W.sstat, W.V64, W.D64, W.part, p.mb_pad, tri);
   else
     k_rot64<1><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, (int)p.pL, W.Zt, W.Gp, p.mb_pad, m_pad, W.X64, p.n_pad,
-                                           W.Qt, W.sstat, nullptr, nullptr, nullptr, 0);
+                                           W.Qt, W.sstat, nullptr, nullptr, nullptr, 0, tri);
   return hipGetLastError();
 }
 

@@ -57,7 +57,7 @@ constexpr int ROT_RG_DEFAULT = 2;  // XCD grid: rg row groups x 8 / rg SNP group
 
 template <int PL, int EPI, int CT, int WR, int WC>
 __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2)
-    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, const int8_t* __restrict__ Zd,
+    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri, const int8_t* __restrict__ Zd,
              const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
              double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
              const double* __restrict__ Dv, double* __restrict__ part) {
@@ -71,11 +71,15 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
   const int64_t ntm = np / BM;
   const int64_t sg = 8 / rg, gm = (ntm + rg - 1) / rg, gn = (ntn + sg - 1) / sg;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
-  const int64_t tm = (xcd % rg) * gm + idx % gm, tn = (xcd / rg) * gn + idx / gm;
-  if (tm >= ntm || tn >= ntn || idx >= gm * gn) return;
+  // lower-triangular Z^T (CLAK-Chol): row tile tm needs the first tm + 1 K
+  // tiles only; the row tiles of a row group are interleaved across the row
+  // groups (equal work per XCD) and taken heaviest first
+  const int64_t tm = tri ? ntm - 1 - ((idx % gm) * rg + xcd % rg) : (xcd % rg) * gm + idx % gm;
+  const int64_t tn = (xcd / rg) * gn + idx / gm;
+  if (tm < 0 || tm >= ntm || tn >= ntn || idx >= gm * gn) return;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t zplane = np * np;
-  const int KT = (int)(np / BK);
+  const int KT = (int)((tri ? min(np, m0 + BM) : np) / BK);
 
   v16i acc[CT][4];
 #pragma unroll
@@ -315,13 +319,14 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   const Workspace& W = p.ws;
   const int64_t ntn = roundup(m_blk, SNP_PAD) / BN, ntm = p.n_pad / ROT_BM;
   const int rg = p.rot_rg ? p.rot_rg : ROT_RG_DEFAULT;
+  const int tri = (p.flags & CLAK_CHOL) ? 1 : 0;
   const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
   dim3 grid((unsigned)(8 * gm * gn));
   dim3 block(64 * WR * WC);
 #define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                         \
   case PLV:                                                                                                        \
-    k_rot_i8<PLV, EPI, CT, WR, WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, W.Zd, W.zs,     \
-                                                                 W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);             \
+    k_rot_i8<PLV, EPI, CT, WR, WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd,      \
+                                                                 W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);       \
     break;
   if (p.fused_t1) {
     switch (p.pL) {

@@ -46,3 +46,6 @@ def test_host_only_calls_without_a_gpu():
     assert lib.clak_autotune(None, 1, None, 0, 1, None, None, 0, 1, None, None) == clak.CLAK_E_ARG
     assert lib.clak_estimate_vc(None, None, 1, clak.CLAK_VC_REML, None, None, None) == clak.CLAK_E_ARG
     assert b"null" in lib.clak_last_error()
+    h = ctypes.c_void_p()
+    assert lib.clak_plan_create(ctypes.byref(h), 10, 3, 2, 10, 0, clak.CLAK_CHOL) == clak.CLAK_E_ARG
+    assert b"t = 1" in lib.clak_last_error()
