@@ -122,7 +122,8 @@ def make_plan(clak, torch, w, block, precision, flags=0):
     Y = torch.from_numpy(np.ascontiguousarray(w.Y.T)).cuda().t()
     # variance components of every trait by REML (timed only: the scan below
     # uses the h2, s2 the phenotypes were drawn with, as the CPU baseline does)
-    clak.clak_estimate_vc(plan.handle, Y, clak.CLAK_VC_REML)
+    if not flags & clak.CLAK_CHOL:
+        clak.clak_estimate_vc(plan.handle, Y, clak.CLAK_VC_REML)
     t3 = time.perf_counter()
     clak.clak_set_traits(plan.handle, Y, torch.from_numpy(w.h2).cuda(), torch.from_numpy(w.s2).cuda())
     t4 = time.perf_counter()
@@ -336,6 +337,23 @@ def main():
                              "stage_ms_per_step": {k: v[0] for k, v in prof64.items()}}
         out["mixed_over_fp64"] = ms64 / ms
         log(f"[bench] FP64 plain path: {ms64:.3f} ms/step")
+
+    if not args.no_compare and w.t == 1:
+        # the single-trait CLAK-Chol route on the same inputs (cross-check and
+        # comparison; the headline line above is CLAK-Eig)
+        torch.cuda.empty_cache()
+        pc, setup_c = make_plan(clak, torch, w, block, args.precision, clak.CLAK_CHOL)
+        if not args.no_tune:
+            clak.clak_autotune(pc.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
+        bc, sc = torch.empty_like(b), torch.empty_like(se)
+        msc, profc = timed_steps(clak, torch, pc, G, bc, sc, block, args.steps, args.warmup, args.eager, pv)
+        pc.close()
+        zc = (bc.double() - b.double()).abs() / se.double()
+        out["clak_chol"] = {"value": cells / (msc * 1e-3), "ms_per_step": msc,
+                            "stage_ms_per_step": {k: v[0] for k, v in profc.items()},
+                            "setup_ms": {k: v for k, v in setup_c.items() if k != "vc_reml_ms"},
+                            "max_abs_diff_vs_eig_in_se_units": float(zc.max().item())}
+        log(f"[bench] CLAK-Chol: {msc:.3f} ms/step, max |b_chol - b_eig| / SE = {zc.max().item():.3e}")
 
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")

@@ -259,8 +259,8 @@ clak_status clak_batch_destroy(clak_batch_t batch);
 
 /* Launch parameters of the mixed path's kernels, all of which leave every
  * result bitwise unchanged (they only change how tiles map to work-groups):
- *   rot_cfg : the rotation's tile configuration, 64-row tiles of 128 or 256
- *             SNPs with two, four or eight waves (0 to 3);
+ *   rot_cfg : the rotation's tile configuration, 64-row tiles of 64, 128 or
+ *             256 SNPs with two, four or eight waves (0 to 4);
  *   rot_rg  : the rotation's XCD row groups (1, 2, 4, 8; the 8 XCDs split into
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
  *   grid_tt : traits per work-group of the grid contraction (32 or 64);

@@ -571,7 +571,7 @@ clak_status clak_plan_set_tuning(clak_plan_t h, int rot_cfg, int rot_rg, int gri
   Plan* p = as_plan(h);
   if (!p) return fail(CLAK_E_ARG, "plan_set_tuning: null plan");
   auto pow2_le8 = [](int v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
-  if (rot_cfg < 0 || rot_cfg > 3 || !pow2_le8(rot_rg) || !pow2_le8(grid_xt) ||
+  if (rot_cfg < 0 || rot_cfg >= ROT_CONFIGS || !pow2_le8(rot_rg) || !pow2_le8(grid_xt) ||
       !(grid_tt == 0 || grid_tt == 32 || grid_tt == 64))
     return fail(CLAK_E_ARG, "plan_set_tuning: rot_cfg=%d rot_rg=%d grid_tt=%d grid_xt=%d outside the tunable set",
                 rot_cfg, rot_rg, grid_tt, grid_xt);
@@ -664,7 +664,7 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   p->rot_rg = 0;
   float best_t = MARGIN * time_ms([&] { return launch_rotate_snps(*p, m_blk); });
   int best_cfg = 0, best_rg = 0;
-  for (int cfg = 0; cfg < 4; ++cfg)
+  for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
     for (int rg : pow2) {
       p->rot_cfg = cfg;
       p->rot_rg = rg;

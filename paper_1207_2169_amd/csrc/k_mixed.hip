@@ -55,8 +55,15 @@ __device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
 
 constexpr int ROT_RG_DEFAULT = 2;  // XCD grid: rg row groups x 8 / rg SNP groups
 
+// Waves per SIMD the register budget is cut for: three for the one-column-tile
+// configuration (64 accumulation registers), else one or two.
+template <int PL, int EPI, int CT>
+constexpr int rot_waves() {
+  return CT == 1 ? (PL <= 4 ? 3 : 2) : ((CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2);
+}
+
 template <int PL, int EPI, int CT, int WR, int WC>
-__global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2)
+__global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri, const int8_t* __restrict__ Zd,
              const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
              double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
@@ -66,6 +73,13 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
   constexpr int A_LD = 16 * BM / NT, B_LD = 4 * BN / NT;  // 16-byte loads per thread per slice
   static_assert(16 * BM % NT == 0 && 4 * BN % NT == 0, "tile / thread mismatch");
   __shared__ __attribute__((aligned(16))) int8_t smem[2 * (A_STAGE + B_STAGE)];
+  // epilogue tables, fetched while the first stage loads
+  constexpr int NTAB = BM * PL + BM + BN * PL + (EPI == 1 ? BM * NP : 0);
+  __shared__ double tab[NTAB];
+  double* Qs = tab;             // [BM][PL]   (Z^T Q_L) rows of the tile
+  double* zS = Qs + BM * PL;    // [BM]       digit scales of Z^T rows
+  double* vS = zS + BM;         // [BN][PL]   centring coefficients of the SNPs
+  double* Vs = vS + BN * PL;    // [BM][NP]   trait operand rows (EPI 1)
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid / WC, wc = wid % WC;
   const int64_t ntm = np / BM;
@@ -126,6 +140,17 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
   };
 
   gload(0);
+  {
+    const int64_t ss = snp_stride(PL);
+    for (int e = tid; e < BM * PL; e += NT) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
+    for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
+    for (int e = tid; e < BN * PL; e += NT) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
+    if (EPI == 1)
+      for (int e = tid; e < BM * NP; e += NT) {
+        const int r = e / NP, q = e % NP;
+        Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
+      }
+  }
   lstore(0);
   __syncthreads();
   if (KT > 1) gload(1);
@@ -165,23 +190,10 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
       lo[ct][e] = acc[ct][2][e] * 256 + acc[ct][3][e];
     }
 
-  // epilogue tables in LDS (the staging buffers are free after the last barrier)
-  double* Qs = (double*)smem;   // [BM][PL]   (Z^T Q_L) rows of the tile
-  double* zS = Qs + BM * PL;    // [BM]       digit scales of Z^T rows
-  double* vS = zS + BM;         // [BN][PL]   centring coefficients of the SNPs
-  double* Vs = vS + BN * PL;    // [BM][NP]   trait operand rows (EPI 1)
-  double* Ps = Vs + BM * NP;    // [WR][BN][NP] per-wave-row partial sums (EPI 1)
-  static_assert((BM * (PL + 1 + NP) + BN * PL + WR * BN * NP) * 8 <= 2 * (A_STAGE + B_STAGE), "LDS reuse");
+  // per-wave-row partial sums (EPI 1) reuse the staging buffers, free after the last barrier
+  double* Ps = (double*)smem;  // [WR][BN][NP]
+  static_assert(WR * BN * NP * 8 <= 2 * (A_STAGE + B_STAGE), "LDS reuse");
   const int64_t ss = snp_stride(PL);
-  for (int e = tid; e < BM * PL; e += NT) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
-  for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
-  for (int e = tid; e < BN * PL; e += NT) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
-  if (EPI == 1)
-    for (int e = tid; e < BM * NP; e += NT) {
-      const int r = e / NP, q = e % NP;
-      Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
-    }
-  __syncthreads();
 
   // one column tile at a time
 #pragma unroll
@@ -251,7 +263,10 @@ __global__ void __launch_bounds__(64 * WR * WC, (CT > 2 || (EPI == 1 && PL > 3))
 //   1: 4, 2, 1   64 x 128 tile, 2 waves, four column tiles per wave
 //   2: 2, 2, 4   64 x 256 tile, 8 waves
 //   3: 4, 2, 2   64 x 256 tile, 4 waves, four column tiles per wave
-constexpr int ROT_BM = 64, ROT_NCFG = 4;
+//   4: 1, 2, 2   64 x 64 tile, 4 waves, one column tile per wave (three
+//                work-groups per CU: more loads in flight per CU)
+constexpr int ROT_BM = 64;
+static_assert(ROT_CONFIGS == 5, "rotation configurations");
 static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0, "rotation tiles must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
@@ -357,6 +372,8 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
       return rotate_cfg<2, 2, 4>(p, m_blk);
     case 3:
       return rotate_cfg<4, 2, 2>(p, m_blk);
+    case 4:
+      return rotate_cfg<1, 2, 2>(p, m_blk);
     default:
       return rotate_cfg<2, 2, 2>(p, m_blk);
   }

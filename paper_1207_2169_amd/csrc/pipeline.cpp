@@ -4,9 +4,11 @@
 //
 // Within a plan, blocks alternate between the two workspace slots: block b is
 // ingested on a side stream into slot b % 2 (after block b - 2, the previous
-// user of that slot, has finished) while block b - 1 is rotated and reduced on
-// the main stream, so the memory-bound ingest overlaps the MFMA-bound
-// rotation.  A launch enqueues the whole schedule from the host: the side and
+// user of that slot, has finished) while block b - 1 is rotated and reduced,
+// so the memory-bound ingest overlaps the MFMA-bound rotation.  Each slot has
+// its own compute stream, so the kernels of block b + 1 start while the last
+// work-groups of block b drain (every buffer a block writes belongs to its
+// slot or to its own outputs).  A launch enqueues the whole schedule from the host: the side and
 // main streams are forked from the launch stream by an event and joined back
 // to it at the end, so the launch stream sees the pipeline as one unit of work.
 // Cohorts of a batch get their own stream pairs and run concurrently.
@@ -20,10 +22,10 @@ namespace {
 
 struct PlanStreams {
   Plan* plan = nullptr;
-  hipStream_t s_main = nullptr, s_in = nullptr;
+  hipStream_t s_main[NSLOTS] = {nullptr, nullptr}, s_in = nullptr;
   hipEvent_t ingested[NSLOTS] = {nullptr, nullptr};
   hipEvent_t done[NSLOTS] = {nullptr, nullptr};
-  hipEvent_t joined_in = nullptr, joined_main = nullptr;
+  hipEvent_t joined_in = nullptr, joined_main[NSLOTS] = {nullptr, nullptr};
   int64_t first = 0, count = 0;  // blocks [first, first + count) of the block list
 };
 
@@ -37,15 +39,16 @@ struct Schedule {
 void release(Schedule* g) {
   if (!g) return;
   for (auto& c : g->ps) {
-    if (c.s_main) (void)hipStreamSynchronize(c.s_main);
+    for (int k = 0; k < NSLOTS; ++k)
+      if (c.s_main[k]) (void)hipStreamSynchronize(c.s_main[k]);
     if (c.s_in) (void)hipStreamSynchronize(c.s_in);
     for (int k = 0; k < NSLOTS; ++k) {
       if (c.ingested[k]) (void)hipEventDestroy(c.ingested[k]);
       if (c.done[k]) (void)hipEventDestroy(c.done[k]);
+      if (c.joined_main[k]) (void)hipEventDestroy(c.joined_main[k]);
+      if (c.s_main[k]) (void)hipStreamDestroy(c.s_main[k]);
     }
     if (c.joined_in) (void)hipEventDestroy(c.joined_in);
-    if (c.joined_main) (void)hipEventDestroy(c.joined_main);
-    if (c.s_main) (void)hipStreamDestroy(c.s_main);
     if (c.s_in) (void)hipStreamDestroy(c.s_in);
   }
   if (g->fork) (void)hipEventDestroy(g->fork);
@@ -70,14 +73,14 @@ clak_status make_schedule(Schedule* g, const std::vector<Plan*>& plans, const st
     c.plan = plans[k];
     c.first = off[k];
     c.count = off[k + 1] - off[k];
-    CK(hipStreamCreateWithFlags(&c.s_main, hipStreamNonBlocking), what);
     CK(hipStreamCreateWithFlags(&c.s_in, hipStreamNonBlocking), what);
     for (int q = 0; q < NSLOTS; ++q) {
+      CK(hipStreamCreateWithFlags(&c.s_main[q], hipStreamNonBlocking), what);
       CK(hipEventCreateWithFlags(&c.ingested[q], hipEventDisableTiming), what);
       CK(hipEventCreateWithFlags(&c.done[q], hipEventDisableTiming), what);
+      CK(hipEventCreateWithFlags(&c.joined_main[q], hipEventDisableTiming), what);
     }
     CK(hipEventCreateWithFlags(&c.joined_in, hipEventDisableTiming), what);
-    CK(hipEventCreateWithFlags(&c.joined_main, hipEventDisableTiming), what);
   }
   return CLAK_OK;
 }
@@ -87,21 +90,23 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
   CK(hipEventRecord(g->fork, origin), what);
   for (auto& c : g->ps) {
     Plan* p = c.plan;
-    CK(hipStreamWaitEvent(c.s_main, g->fork, 0), what);
+    for (int q = 0; q < NSLOTS; ++q) CK(hipStreamWaitEvent(c.s_main[q], g->fork, 0), what);
     CK(hipStreamWaitEvent(c.s_in, g->fork, 0), what);
     for (int64_t j = 0; j < c.count; ++j) {
       const int slot = (int)(j % NSLOTS);
       if (j >= NSLOTS) CK(hipStreamWaitEvent(c.s_in, c.done[slot], 0), what);
       const clak_block& B = g->blocks[c.first + j];
-      clak_status st = enqueue_block(p, slot, c.s_in, c.s_main, c.ingested[slot], B.m_blk, B.G, g->g_dtype, B.ldg,
-                                     cell_out(B.b, B.se, B.pval, B.flags, B.ldo, g->out_dtype));
+      clak_status st = enqueue_block(p, slot, c.s_in, c.s_main[slot], c.ingested[slot], B.m_blk, B.G, g->g_dtype,
+                                     B.ldg, cell_out(B.b, B.se, B.pval, B.flags, B.ldo, g->out_dtype));
       if (st) return st;
-      CK(hipEventRecord(c.done[slot], c.s_main), what);
+      CK(hipEventRecord(c.done[slot], c.s_main[slot]), what);
     }
     CK(hipEventRecord(c.joined_in, c.s_in), what);
-    CK(hipEventRecord(c.joined_main, c.s_main), what);
     CK(hipStreamWaitEvent(origin, c.joined_in, 0), what);
-    CK(hipStreamWaitEvent(origin, c.joined_main, 0), what);
+    for (int q = 0; q < NSLOTS; ++q) {
+      CK(hipEventRecord(c.joined_main[q], c.s_main[q]), what);
+      CK(hipStreamWaitEvent(origin, c.joined_main[q], 0), what);
+    }
   }
   return CLAK_OK;
 }
