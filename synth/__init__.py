@@ -7,6 +7,7 @@ holds none of the association method's arithmetic.
 """
 from .genotypes import snp_genotypes, allele_thresholds
 from .workloads import CONFIGS, Workload, make_workload, cohort_workloads
+from .bedfile import pack_rows, write_bed
 
 __all__ = ["snp_genotypes", "allele_thresholds", "CONFIGS", "Workload",
-           "make_workload", "cohort_workloads"]
+           "make_workload", "cohort_workloads", "pack_rows", "write_bed"]
