@@ -99,9 +99,18 @@ typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_pre
                                and clak_estimate_vc need eigenpairs and return
                                CLAK_E_UNSUPPORTED for such a plan.              */
 
-/* Genotype element types accepted by clak_run_block (values 0, 1, 2). */
+/* Genotype element types accepted by clak_run_block (values 0, 1, 2).
+ *   CLAK_G_U8 : one byte per individual; ldg in elements.
+ *   CLAK_G_F16: one half per individual; ldg in elements.
+ *   CLAK_G_P2 : the SNP-major 2-bit codes of the PLINK 1 binary genotype
+ *               format, four individuals per byte, individual i in bits
+ *               2 (i % 4) and 2 (i % 4) + 1 of byte i / 4 of its SNP row;
+ *               codes 00, 10, 11 are 2, 1, 0 copies of the first allele and
+ *               01 is missing (the SNP is flagged CLAK_CELL_BAD_GENOTYPE);
+ *               ldg in bytes, at least (n + 3) / 4. */
 #define CLAK_G_U8 0
 #define CLAK_G_F16 1
+#define CLAK_G_P2 2
 /* Output element types. */
 #define CLAK_OUT_F32 0
 #define CLAK_OUT_F64 1
@@ -109,7 +118,7 @@ typedef enum clak_precision { CLAK_PREC_FP64 = 0, CLAK_PREC_MIXED = 1 } clak_pre
 /* Per-cell flag values written by clak_run_block. */
 #define CLAK_CELL_OK 0
 #define CLAK_CELL_DEGENERATE 1  /* g_i in span(X_L) (or numerically so): b and SE are NaN */
-#define CLAK_CELL_BAD_GENOTYPE 2 /* a genotype of the SNP is not 0, 1 or 2: b and SE are NaN */
+#define CLAK_CELL_BAD_GENOTYPE 2 /* a genotype of the SNP is not 0, 1 or 2 (or is missing): b and SE are NaN */
 
 typedef struct clak_plan_s* clak_plan_t;
 
@@ -192,7 +201,7 @@ clak_status clak_estimate_vc(clak_plan_t plan, const double* d_Y, int64_t ldy, i
  * p-value of the SNP effect (the estimates come with their p-values in the
  * problem statement of section 1).  Asynchronous.
  *   d_G     : n x m_blk genotypes (column = one SNP), element type g_dtype,
- *             leading dimension ldg >= n (in elements).
+ *             leading dimension ldg (one row of n genotypes at least).
  *   d_b     : SNP effects; with CLAK_OUT_SNP element (i, j) at d_b[i + j*ldo],
  *             with CLAK_OUT_FULL component c at d_b[(i + j*ldo)*p + c].
  *   d_se    : standard error of the SNP effect, element (i, j) at d_se[i + j*ldo].
@@ -283,6 +292,34 @@ clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, in
  * to tune and runs the block.  Errors: as clak_run_block, CLAK_E_DEVICE. */
 clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, const char* cache_path);
+
+/* Out-of-core genotype input.  A SNP-major PLINK 1 binary genotype file (the
+ * bytes 0x6c 0x1b 0x01, then m rows of (n + 3) / 4 bytes in the CLAK_G_P2
+ * coding) is read block by block by a host thread into `depth` (2 to 16)
+ * pinned host buffers of `block` rows; clak_bed_scan streams the blocks
+ * through the plan's two-slot pipeline as they arrive (the ingest reads each
+ * block from pinned memory over PCIe, or through the copy engine with
+ * CLAK_STAGE_GENOTYPES), so disk reads, transfers and kernels overlap; a
+ * buffer is refilled once the ingest that read it has completed.  The blocks
+ * of X_R come from disk while earlier ones are processed, as in the
+ * streaming of section 3.
+ *   clak_bed_open : checks the magic bytes and the size 3 + m (n + 3) / 4,
+ *                   allocates the buffers and starts the reader.  Errors:
+ *                   CLAK_E_ARG (missing file, wrong magic or size, depth),
+ *                   CLAK_E_DEVICE.
+ *   clak_bed_scan : every SNP of the file through `plan` (n of the plan, block
+ *                   <= max_block, READY); outputs as for clak_run_block with SNP
+ *                   i of the file at index i (ldo >= m), d_flags and d_pval
+ *                   nullable.  Synchronous (returns when the plan's stream has
+ *                   finished).  One scan per opened reader (CLAK_E_STATE after).
+ *                   Errors: CLAK_E_ARG (read failure, sizes), CLAK_E_STATE,
+ *                   CLAK_E_DEVICE.
+ *   clak_bed_close: stops the reader, frees the buffers, closes the file. */
+typedef struct clak_bed_s* clak_bed_t;
+clak_status clak_bed_open(clak_bed_t* bed, const char* path, int64_t n, int64_t m, int64_t block, int depth);
+clak_status clak_bed_scan(clak_bed_t bed, clak_plan_t plan, void* d_b, void* d_se, int out_dtype, int64_t ldo,
+                          uint8_t* d_flags, void* d_pval);
+clak_status clak_bed_close(clak_bed_t bed);
 
 /* Stages of clak_run_block timed by the profiler. */
 #define CLAK_STAGE_INGEST 0  /* genotype block -> int8 panel, per-SNP centring statistics */

@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "CLAK_OK", 1: "CLAK_E_ARG", 2: "CLAK_E_STATE", 3: "CLAK_E_NOT
 CLAK_PREC_FP64, CLAK_PREC_MIXED = 0, 1
 CLAK_VAR_MODEL, CLAK_VAR_PAPER = 0, 1
 CLAK_OUT_SNP, CLAK_OUT_FULL, CLAK_STAGE_GENOTYPES, CLAK_CHOL = 0, 2, 4, 8
-CLAK_G_U8, CLAK_G_F16 = 0, 1
+CLAK_G_U8, CLAK_G_F16, CLAK_G_P2 = 0, 1, 2
 CLAK_OUT_F32, CLAK_OUT_F64 = 0, 1
 CLAK_VC_ML, CLAK_VC_REML = 0, 1
 CLAK_CELL_OK, CLAK_CELL_DEGENERATE, CLAK_CELL_BAD_GENOTYPE = 0, 1, 2
@@ -56,6 +56,9 @@ SIGNATURES = {
     "clak_plan_get_tuning": (_I, [_P, _P, _P, _P, _P]),
     "clak_autotune": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, ctypes.c_char_p]),
     "clak_plan_get_profile": (_I, [_P, _P, _P]),
+    "clak_bed_open": (_I, [ctypes.POINTER(_P), ctypes.c_char_p, _I64, _I64, _I64, _I]),
+    "clak_bed_scan": (_I, [_P, _P, _P, _P, _I, _I64, _P, _P]),
+    "clak_bed_close": (_I, [_P]),
     "clak_last_error": (ctypes.c_char_p, []),
     "clak_version": (ctypes.c_char_p, []),
 }
@@ -200,11 +203,48 @@ def clak_estimate_vc(plan: int, Y: torch.Tensor, method: int = CLAK_VC_REML, h2:
 
 
 def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
-                   flags: Optional[torch.Tensor] = None, pval: Optional[torch.Tensor] = None):
-    """G: (m_blk, ldg) uint8 or float16 SNP rows; b, se, pval: (t, ldo[, p]) float32/64."""
-    blk, gdt, odt = _block_args(G, b, se, flags, pval)
+                   flags: Optional[torch.Tensor] = None, pval: Optional[torch.Tensor] = None,
+                   g_dtype: Optional[int] = None):
+    """G: (m_blk, ldg) uint8 or float16 SNP rows (uint8 rows of 2-bit codes with g_dtype=CLAK_G_P2);
+    b, se, pval: (t, ldo[, p]) float32/64."""
+    blk, gdt, odt = _block_args(G, b, se, flags, pval, g_dtype)
     _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags,
                                 blk.pval), "clak_run_block")
+
+
+def clak_bed_open(path: str, n: int, m: int, block: int, depth: int = 4) -> int:
+    """Reader of a SNP-major PLINK 1 binary genotype file (n individuals, m SNPs) in blocks of `block` SNPs."""
+    h = _P()
+    _check(lib().clak_bed_open(ctypes.byref(h), os.fsencode(path), n, m, block, depth), "clak_bed_open")
+    return h.value
+
+
+def clak_bed_scan(bed: int, plan: int, b: torch.Tensor, se: torch.Tensor, flags: Optional[torch.Tensor] = None,
+                  pval: Optional[torch.Tensor] = None):
+    """Every SNP of the file through the plan; b, se, flags, pval: (t, ldo[, p]) with ldo >= m (synchronous)."""
+    for name, x in (("b", b), ("se", se)):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda):
+            raise ValueError(f"{name} must be a GPU tensor")
+    if b.dtype != se.dtype or b.dtype not in (torch.float32, torch.float64):
+        raise ValueError("b and se must share dtype float32 or float64")
+    if se.dim() != 2 or se.stride(1) != 1:
+        raise ValueError("se must be (t, ldo) with contiguous rows")
+    ldo = se.stride(0) if se.shape[0] > 1 else se.shape[1]
+    fptr = pptr = None
+    if flags is not None:
+        if flags.dtype != torch.uint8 or flags.shape != se.shape or flags.stride() != se.stride():
+            raise ValueError("flags must be uint8 with the layout of se")
+        fptr = flags.data_ptr()
+    if pval is not None:
+        if pval.dtype != se.dtype or pval.shape != se.shape or pval.stride() != se.stride():
+            raise ValueError("pval must match se")
+        pptr = pval.data_ptr()
+    odt = CLAK_OUT_F32 if b.dtype == torch.float32 else CLAK_OUT_F64
+    _check(lib().clak_bed_scan(bed, plan, b.data_ptr(), se.data_ptr(), odt, ldo, fptr, pptr), "clak_bed_scan")
+
+
+def clak_bed_close(bed: int):
+    _check(lib().clak_bed_close(bed), "clak_bed_close")
 
 
 def clak_plan_set_tuning(plan: int, rot_cfg: int = 0, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
@@ -239,10 +279,14 @@ def clak_plan_get_profile(plan: int):
     return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
 
 
-def _block_args(G, b, se, flags=None, pval=None):
+def _block_args(G, b, se, flags=None, pval=None, g_dtype=None):
     """(clak_block, g_dtype, out_dtype) for one block, with the checks of clak_run_block."""
     _dev(G, "G")
-    if G.dtype == torch.uint8:
+    if g_dtype == CLAK_G_P2:
+        if G.dtype != torch.uint8:
+            raise ValueError("2-bit genotype rows must be a uint8 tensor")
+        gdt = CLAK_G_P2
+    elif G.dtype == torch.uint8:
         gdt = CLAK_G_U8
     elif G.dtype == torch.float16:
         gdt = CLAK_G_F16

@@ -485,10 +485,13 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
     return fail(CLAK_E_ARG, "run_block: m_blk=%lld outside [1, max_block=%lld]", (long long)m_blk,
                 (long long)p->max_block);
   if (!d_G || !d_b || !d_se) return fail(CLAK_E_ARG, "run_block: null G, b or se");
-  if (g_dtype != CLAK_G_U8 && g_dtype != CLAK_G_F16) return fail(CLAK_E_ARG, "run_block: unknown g_dtype %d", g_dtype);
+  if (g_dtype != CLAK_G_U8 && g_dtype != CLAK_G_F16 && g_dtype != CLAK_G_P2)
+    return fail(CLAK_E_ARG, "run_block: unknown g_dtype %d", g_dtype);
   if (out_dtype != CLAK_OUT_F32 && out_dtype != CLAK_OUT_F64)
     return fail(CLAK_E_ARG, "run_block: unknown out_dtype %d", out_dtype);
-  if (ldg < p->n) return fail(CLAK_E_ARG, "run_block: ldg=%lld < n", (long long)ldg);
+  if (ldg < genotype_row_units(g_dtype, p->n))
+    return fail(CLAK_E_ARG, "run_block: ldg=%lld < %lld (one genotype row)", (long long)ldg,
+                (long long)genotype_row_units(g_dtype, p->n));
   if (ldo < m_blk) return fail(CLAK_E_ARG, "run_block: ldo=%lld < m_blk", (long long)ldo);
   const size_t esz = out_dtype == CLAK_OUT_F32 ? 4 : 8;
   if (!aligned(d_b, esz) || !aligned(d_se, esz) || !aligned(d_pval, esz))
@@ -522,7 +525,7 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
   // CLAK_STAGE_GENOTYPES: the copy engine moves the block into the slot's staging buffer, the ingest reads it there
   const void* G = d_G;
   int64_t ld = ldg;
-  const int64_t esz = g_dtype == CLAK_G_F16 ? 2 : 1;
+  const int64_t esz = g_dtype == CLAK_G_F16 ? 2 : 1;  // bytes per unit of ldg
   const bool stage_copy = p->ws.slot[slot].Gh != nullptr;
   if (stage_copy) {
     G = p->ws.slot[slot].Gh;
@@ -530,8 +533,8 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
   }
   e = staged(CLAK_STAGE_INGEST, [&] {
     if (stage_copy) {
-      hipError_t c = hipMemcpy2DAsync(p->ws.slot[slot].Gh, host_pitch(p->n), d_G, ldg * esz, p->n * esz, m_blk,
-                                      hipMemcpyDefault, p->stream);
+      hipError_t c = hipMemcpy2DAsync(p->ws.slot[slot].Gh, host_pitch(p->n), d_G, ldg * esz,
+                                      genotype_row_units(g_dtype, p->n) * esz, m_blk, hipMemcpyDefault, p->stream);
       if (c != hipSuccess) return c;
     }
     return launch_ingest(*p, m_blk, G, g_dtype, ld);

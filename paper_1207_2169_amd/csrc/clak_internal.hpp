@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/clak.h"
@@ -78,6 +79,9 @@ constexpr int NSLOTS = 2;
 
 // Row pitch (bytes) of the host-block staging buffer: n elements of up to 2 bytes, 16-byte aligned rows.
 inline int64_t host_pitch(int64_t n) { return (2 * n + 15) / 16 * 16; }
+// Units of ldg one genotype row of n individuals takes: n elements (u8, f16)
+// or (n + 3) / 4 bytes (2-bit codes).
+inline int64_t genotype_row_units(int g_dtype, int64_t n) { return g_dtype == CLAK_G_P2 ? (n + 3) / 4 : n; }
 
 struct Workspace {
   Slot slot[NSLOTS];
@@ -179,6 +183,9 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
                            const void* d_se, int out_dtype, int64_t ldo, const void* d_flags, const void* d_pval);
 clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
                           int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const CellOut& out);
+clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
+                          const std::function<clak_status(int64_t, clak_block*)>& get,
+                          const std::function<clak_status(int64_t, hipStream_t)>& after, const char* what);
 
 // ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
 // set-up

@@ -14,10 +14,18 @@ namespace clak {
 // the window's 128 rows of Q_L are staged in LDS (read back as wave-uniform
 // broadcasts).  The work-group writes the int8 panel rows of its windows and
 // one partial (Q_L^T g, g^T g, invalid-genotype count) per SNP.
-// ALIGN is the byte alignment shared by G and its leading dimension (u8).
+// ALIGN is the byte alignment shared by G and its leading dimension (u8, and
+// for 2-bit rows whether 4-byte words can be read).  KIND: 0 u8, 1 f16, 2
+// 2-bit codes, four individuals per byte, individual i in bits 2 (i % 4) and
+// 2 (i % 4) + 1 of byte i / 4: 00 -> 2, 10 -> 1, 11 -> 0 copies of the first
+// allele, 01 -> missing (an invalid genotype).
 constexpr int ING_WAVES = 8;
 
-template <int PL, int ALIGN, bool F16>
+// genotype of a 2-bit code (3 stands for missing)
+// (byte c of 0x00010302 is the value of code c: 2, 3, 1, 0)
+__device__ __forceinline__ uint8_t p2_value(uint32_t code) { return (uint8_t)((0x00010302u >> (8 * code)) & 0xffu); }
+
+template <int PL, int ALIGN, int KIND>
 __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np, int64_t m_blk, int64_t m_pad,
                                                            int64_t mbp, const void* __restrict__ G, int64_t ldg,
                                                            const double* __restrict__ QL, int8_t* __restrict__ Gp,
@@ -43,7 +51,19 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
 #pragma unroll
     for (int e = 0; e < 16; ++e) by[e] = 0;
     if (snp < m_blk) {
-      if (F16) {
+      if (KIND == 2) {
+        const uint8_t* row = (const uint8_t*)G + snp * ldg + i0 / 4;
+        uint32_t word = 0;
+        if (i0 + 16 <= n && ALIGN >= 4) {
+          word = *(const uint32_t*)__builtin_assume_aligned(row, 4);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i0 + 4 * e < n) word |= (uint32_t)row[e] << (8 * e);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) by[e] = (i0 + e < n) ? p2_value((word >> (2 * e)) & 3u) : 0;
+      } else if (KIND == 1) {
         const __half* row = (const __half*)G + snp * ldg + i0;
 #pragma unroll
         for (int e = 0; e < 16; ++e)
@@ -144,15 +164,23 @@ static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const v
   const Workspace& W = p.ws;
   const dim3 block(64 * ING_WAVES);
   if (g_dtype == CLAK_G_F16) {
-    k_ingest<PL, 1, true><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
-                                                        W.ipart);
+    k_ingest<PL, 1, 1><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
+                                                     W.ipart);
+  } else if (g_dtype == CLAK_G_P2) {
+    const bool words = ((uintptr_t)d_G % 4 == 0) && (ldg % 4 == 0);
+    if (words)
+      k_ingest<PL, 4, 2><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
+                                                       W.ipart);
+    else
+      k_ingest<PL, 1, 2><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
+                                                       W.ipart);
   } else {
     // widest alignment shared by the base address and the row pitch, capped at 16
     const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
     const int align = (int)(bits & (~bits + 1));
 #define CLAK_ING(A)                                                                                               \
-  k_ingest<PL, A, false><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, \
-                                                       W.ipart)
+  k_ingest<PL, A, 0><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, \
+                                                   W.ipart)
     if (align >= 16)
       CLAK_ING(16);
     else if (align >= 8)

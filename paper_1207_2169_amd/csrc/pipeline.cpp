@@ -12,6 +12,7 @@
 // main streams are forked from the launch stream by an event and joined back
 // to it at the end, so the launch stream sees the pipeline as one unit of work.
 // Cohorts of a batch get their own stream pairs and run concurrently.
+#include <functional>
 #include <vector>
 
 #include "clak_internal.hpp"
@@ -121,6 +122,59 @@ clak_status check_blocks(Plan* p, int64_t n, const clak_block* blocks, int g_dty
 }
 
 }  // namespace
+
+namespace clak {
+
+// Streams n_blocks blocks of one plan through the two-slot, per-slot-stream
+// schedule of a pipeline, asking `get` for each block just before it is
+// enqueued (it may wait, e.g. for a file read) and calling `after` with the
+// ingest stream once the block's ingest is enqueued (e.g. to record when its
+// input buffer may be reused).  Forked from and joined back to the plan's
+// stream; returns after the plan's stream has finished the work.
+clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
+                          const std::function<clak_status(int64_t, clak_block*)>& get,
+                          const std::function<clak_status(int64_t, hipStream_t)>& after, const char* what) {
+  std::vector<clak_block> placeholder((size_t)n_blocks);
+  Schedule* g = new Schedule();
+  clak_status s = make_schedule(g, {p}, {0, n_blocks}, placeholder.data(), g_dtype, out_dtype, what);
+  auto done = [&](clak_status st) {
+    release(g);
+    return st;
+  };
+  if (s) return done(s);
+  PlanStreams& c = g->ps[0];
+  auto ck = [&](hipError_t e) -> clak_status {
+    return e == hipSuccess ? CLAK_OK : fail(CLAK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  };
+  if ((s = ck(hipEventRecord(g->fork, p->stream)))) return done(s);
+  for (int q = 0; q < NSLOTS; ++q)
+    if ((s = ck(hipStreamWaitEvent(c.s_main[q], g->fork, 0)))) return done(s);
+  if ((s = ck(hipStreamWaitEvent(c.s_in, g->fork, 0)))) return done(s);
+  clak_status result = CLAK_OK;
+  for (int64_t j = 0; j < n_blocks && result == CLAK_OK; ++j) {
+    const int slot = (int)(j % NSLOTS);
+    clak_block B{};
+    if ((result = get(j, &B))) break;
+    if ((result = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval))) break;
+    if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(c.s_in, c.done[slot], 0)))) break;
+    if ((result = enqueue_block(p, slot, c.s_in, c.s_main[slot], c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
+                                cell_out(B.b, B.se, B.pval, B.flags, B.ldo, out_dtype))))
+      break;
+    if ((result = after(j, c.s_in))) break;
+    result = ck(hipEventRecord(c.done[slot], c.s_main[slot]));
+  }
+  // join everything enqueued so far back to the plan's stream and wait for it
+  clak_status js = ck(hipEventRecord(c.joined_in, c.s_in));
+  if (!js) js = ck(hipStreamWaitEvent(p->stream, c.joined_in, 0));
+  for (int q = 0; q < NSLOTS && !js; ++q) {
+    js = ck(hipEventRecord(c.joined_main[q], c.s_main[q]));
+    if (!js) js = ck(hipStreamWaitEvent(p->stream, c.joined_main[q], 0));
+  }
+  if (!js) js = ck(hipStreamSynchronize(p->stream));
+  return done(result ? result : js);
+}
+
+}  // namespace clak
 
 struct clak_pipeline_s {
   Schedule* run;
