@@ -59,7 +59,7 @@ def parse():
                     help="also time the out-of-core scan: the genotypes written as a PLINK 1 binary file (2-bit "
                          "rows) in the temp directory, read by the library's reader thread into pinned buffers "
                          "and streamed through the pipeline (disk/page cache -> host -> PCIe -> GPU)")
-    ap.add_argument("--bed-depth", type=int, default=4, help="pinned buffers of the file reader")
+    ap.add_argument("--bed-depth", type=int, default=8, help="pinned buffers of the file reader")
     ap.add_argument("--pval", action="store_true",
                     help="also write the two-sided Wald p-value of every cell (fused in the Schur epilogue)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target duration of the oracle sample")
@@ -370,33 +370,32 @@ def main():
         log(f"[bench] wrote {nbytes / 1e6:.0f} MB of 2-bit genotype rows in {time.perf_counter() - t0:.1f} s")
         try:
             torch.cuda.empty_cache()
-            pb, _ = make_plan(clak, torch, w, block, args.precision)
+            pb, _ = make_plan(clak, torch, w, block, args.precision,
+                              clak.CLAK_STAGE_GENOTYPES if args.stage_genotypes else 0)
             if not args.no_tune:
                 clak.clak_autotune(pb.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
             bb, sb = torch.empty_like(b), torch.empty_like(se)
 
-            def scan():
-                h = clak.clak_bed_open(path, w.n, m, block, args.bed_depth)
-                try:
+            h = clak.clak_bed_open(path, w.n, m, block, args.bed_depth)
+            try:
+                clak.clak_bed_scan(h, pb.handle, bb, sb)  # warm: the file is now in the page cache
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = max(1, min(args.steps, 5))
+                for _ in range(reps):
                     clak.clak_bed_scan(h, pb.handle, bb, sb)
-                finally:
-                    clak.clak_bed_close(h)
-
-            scan()  # the file is now in the page cache
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            reps = max(1, min(args.steps, 5))
-            for _ in range(reps):
-                scan()
-            msb = (time.perf_counter() - t0) / reps * 1e3
+                msb = (time.perf_counter() - t0) / reps * 1e3
+            finally:
+                clak.clak_bed_close(h)
             pb.close()
             same = bool(torch.equal(torch.nan_to_num(bb), torch.nan_to_num(b))) if args.precision == "mixed" \
                 and args.no_compare else None
             out["ooc_bed"] = {"value": cells / (msb * 1e-3), "unit": "cells/s", "ms_per_step": msb,
                               "file_bytes": nbytes, "reader_depth": args.bed_depth, "reps": reps,
                               "bitwise_equal_to_resident_run": same,
-                              "note": "host wall clock around open + scan + close; file in the host page cache; "
-                                      "2-bit rows ingested from pinned host memory over PCIe"}
+                              "staged_by_copy_engine": bool(args.stage_genotypes),
+                              "note": "host wall clock per scan of the whole file (reader opened once); file in "
+                                      "the host page cache; 2-bit rows from pinned host buffers over PCIe"}
             log(f"[bench] out-of-core 2-bit file scan: {msb:.3f} ms/step, {cells / msb * 1e3:.4e} cells/s")
         finally:
             os.remove(path)

@@ -311,9 +311,10 @@ clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int 
  *                   <= max_block, READY); outputs as for clak_run_block with SNP
  *                   i of the file at index i (ldo >= m), d_flags and d_pval
  *                   nullable.  Synchronous (returns when the plan's stream has
- *                   finished).  One scan per opened reader (CLAK_E_STATE after).
- *                   Errors: CLAK_E_ARG (read failure, sizes), CLAK_E_STATE,
- *                   CLAK_E_DEVICE.
+ *                   finished).  A finished scan rewinds the reader, so scans
+ *                   can be repeated; after a failed one the reader must be
+ *                   closed (CLAK_E_STATE).  Errors: CLAK_E_ARG (read failure,
+ *                   sizes), CLAK_E_STATE, CLAK_E_DEVICE.
  *   clak_bed_close: stops the reader, frees the buffers, closes the file. */
 typedef struct clak_bed_s* clak_bed_t;
 clak_status clak_bed_open(clak_bed_t* bed, const char* path, int64_t n, int64_t m, int64_t block, int depth);

@@ -527,14 +527,22 @@ clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_mai
   int64_t ld = ldg;
   const int64_t esz = g_dtype == CLAK_G_F16 ? 2 : 1;  // bytes per unit of ldg
   const bool stage_copy = p->ws.slot[slot].Gh != nullptr;
+  const int64_t row_bytes = genotype_row_units(g_dtype, p->n) * esz;
+  // rows that fit the staging pitch keep the caller's pitch and move as one
+  // contiguous copy of the block's exact extent; wider rows are re-pitched
+  const bool stage_flat = stage_copy && ldg * esz <= host_pitch(p->n);
   if (stage_copy) {
     G = p->ws.slot[slot].Gh;
-    ld = host_pitch(p->n) / esz;
+    ld = stage_flat ? ldg : host_pitch(p->n) / esz;
   }
   e = staged(CLAK_STAGE_INGEST, [&] {
-    if (stage_copy) {
-      hipError_t c = hipMemcpy2DAsync(p->ws.slot[slot].Gh, host_pitch(p->n), d_G, ldg * esz,
-                                      genotype_row_units(g_dtype, p->n) * esz, m_blk, hipMemcpyDefault, p->stream);
+    if (stage_flat) {
+      hipError_t c = hipMemcpyAsync(p->ws.slot[slot].Gh, d_G, (size_t)((m_blk - 1) * ldg * esz + row_bytes),
+                                    hipMemcpyDefault, p->stream);
+      if (c != hipSuccess) return c;
+    } else if (stage_copy) {
+      hipError_t c = hipMemcpy2DAsync(p->ws.slot[slot].Gh, host_pitch(p->n), d_G, ldg * esz, row_bytes, m_blk,
+                                      hipMemcpyDefault, p->stream);
       if (c != hipSuccess) return c;
     }
     return launch_ingest(*p, m_blk, G, g_dtype, ld);

@@ -5,6 +5,9 @@
 // copy engine with CLAK_STAGE_GENOTYPES), so that disk reads, PCIe transfers
 // and the per-block kernels overlap (supplementary notes, section 3: the SNP
 // blocks of X_R are streamed from disk while earlier blocks are processed).
+#include <fcntl.h>
+#include <unistd.h>
+
 #include <algorithm>
 #include <condition_variable>
 #include <cstdio>
@@ -18,16 +21,17 @@
 using namespace clak;
 
 struct clak_bed_s {
-  std::FILE* f = nullptr;
+  int fd = -1;
   int64_t n = 0, m = 0, block = 0, row = 0, nblocks = 0;
   int depth = 0;
   std::vector<uint8_t*> buf;       // pinned host buffers, block * row bytes each
   std::vector<hipEvent_t> freed;   // per buffer: recorded after the ingest that read it
   std::vector<char> armed;         // freed[k] has been recorded (guarded by mu)
-  std::thread reader;
+  std::vector<int64_t> holds;      // block whose rows buffer k holds, -1 while being filled (guarded by mu)
+  std::vector<std::thread> readers;
   std::mutex mu;
   std::condition_variable cv;
-  int64_t produced = 0;  // blocks read so far (in order)
+  int64_t claimed = 0;   // blocks handed to reader threads so far (in order)
   int64_t released = 0;  // blocks whose buffer the scan has handed back
   bool stop = false;
   std::string err;
@@ -37,16 +41,17 @@ namespace {
 
 constexpr unsigned char BED_MAGIC[3] = {0x6c, 0x1b, 0x01};
 
+// Reader threads claim blocks in order; block b goes to buffer b % depth once
+// block b - depth has been released by the scan and its ingest has finished.
 void reader_main(clak_bed_s* r) {
   for (;;) {
     int64_t b;
     bool busy;
     {
       std::unique_lock<std::mutex> lk(r->mu);
-      // the next block to read may use buffer (b % depth) once block b - depth has been released
-      r->cv.wait(lk, [&] { return r->stop || (r->produced < r->nblocks && r->produced - r->released < r->depth); });
+      r->cv.wait(lk, [&] { return r->stop || (r->claimed < r->nblocks && r->claimed - r->released < r->depth); });
       if (r->stop) return;
-      b = r->produced;
+      b = r->claimed++;
       busy = r->armed[b % r->depth] != 0;
     }
     const int k = (int)(b % r->depth);
@@ -60,15 +65,19 @@ void reader_main(clak_bed_s* r) {
       }
     }
     const int64_t first = b * r->block, count = std::min(r->block, r->m - first);
-    bool ok = std::fseek(r->f, (long)(3 + first * r->row), SEEK_SET) == 0 &&
-              std::fread(r->buf[k], 1, (size_t)(count * r->row), r->f) == (size_t)(count * r->row);
+    size_t done = 0, want = (size_t)(count * r->row);
+    while (done < want) {
+      const ssize_t got = pread(r->fd, r->buf[k] + done, want - done, (off_t)(3 + first * r->row + (int64_t)done));
+      if (got <= 0) break;
+      done += (size_t)got;
+    }
     std::lock_guard<std::mutex> lk(r->mu);
-    if (!ok) {
+    if (done != want) {
       r->err = "bed reader: short read at SNP " + std::to_string(first);
       r->cv.notify_all();
       return;
     }
-    r->produced = b + 1;
+    r->holds[k] = b;
     r->cv.notify_all();
   }
 }
@@ -80,14 +89,15 @@ void close_bed(clak_bed_s* r) {
     r->stop = true;
   }
   r->cv.notify_all();
-  if (r->reader.joinable()) r->reader.join();
+  for (auto& t : r->readers)
+    if (t.joinable()) t.join();
   for (size_t k = 0; k < r->freed.size(); ++k) {
     if (r->armed[k]) (void)hipEventSynchronize(r->freed[k]);
     if (r->freed[k]) (void)hipEventDestroy(r->freed[k]);
   }
   for (uint8_t* p : r->buf)
     if (p) (void)hipHostFree(p);
-  if (r->f) std::fclose(r->f);
+  if (r->fd >= 0) close(r->fd);
   delete r;
 }
 
@@ -100,23 +110,23 @@ clak_status clak_bed_open(clak_bed_t* out, const char* path, int64_t n, int64_t 
   *out = nullptr;
   if (n < 1 || m < 1 || block < 1) return fail(CLAK_E_ARG, "bed_open: n, m and block must be positive");
   if (depth < 2 || depth > 16) return fail(CLAK_E_ARG, "bed_open: depth=%d outside [2, 16]", depth);
-  std::FILE* f = std::fopen(path, "rb");
-  if (!f) return fail(CLAK_E_ARG, "bed_open: cannot open %s", path);
+  const int fd = open(path, O_RDONLY);
+  if (fd < 0) return fail(CLAK_E_ARG, "bed_open: cannot open %s", path);
   unsigned char magic[3] = {0, 0, 0};
   const int64_t row = (n + 3) / 4;
-  long size = -1;
-  if (std::fread(magic, 1, 3, f) == 3 && std::fseek(f, 0, SEEK_END) == 0) size = std::ftell(f);
-  if (magic[0] != BED_MAGIC[0] || magic[1] != BED_MAGIC[1] || magic[2] != BED_MAGIC[2]) {
-    std::fclose(f);
+  const off_t size = lseek(fd, 0, SEEK_END);
+  if (pread(fd, magic, 3, 0) != 3 || magic[0] != BED_MAGIC[0] || magic[1] != BED_MAGIC[1] ||
+      magic[2] != BED_MAGIC[2]) {
+    close(fd);
     return fail(CLAK_E_ARG, "bed_open: %s is not a SNP-major PLINK 1 binary genotype file", path);
   }
-  if (size != 3 + m * row) {
-    std::fclose(f);
-    return fail(CLAK_E_ARG, "bed_open: %s holds %ld bytes, %lld expected for n=%lld, m=%lld", path, size,
-                (long long)(3 + m * row), (long long)n, (long long)m);
+  if ((int64_t)size != 3 + m * row) {
+    close(fd);
+    return fail(CLAK_E_ARG, "bed_open: %s holds %lld bytes, %lld expected for n=%lld, m=%lld", path,
+                (long long)size, (long long)(3 + m * row), (long long)n, (long long)m);
   }
   clak_bed_s* r = new clak_bed_s();
-  r->f = f;
+  r->fd = fd;
   r->n = n;
   r->m = m;
   r->block = block;
@@ -126,6 +136,7 @@ clak_status clak_bed_open(clak_bed_t* out, const char* path, int64_t n, int64_t 
   r->buf.assign(depth, nullptr);
   r->freed.assign(depth, nullptr);
   r->armed.assign(depth, 0);
+  r->holds.assign(depth, -1);
   for (int k = 0; k < depth; ++k) {
     if (hipHostMalloc((void**)&r->buf[k], (size_t)(block * row), hipHostMallocDefault) != hipSuccess ||
         hipEventCreateWithFlags(&r->freed[k], hipEventDisableTiming) != hipSuccess) {
@@ -134,7 +145,9 @@ clak_status clak_bed_open(clak_bed_t* out, const char* path, int64_t n, int64_t 
       return fail(CLAK_E_DEVICE, "bed_open: pinned buffer or event allocation failed");
     }
   }
-  r->reader = std::thread(reader_main, r);
+  // a few positional readers keep the ring full (one thread reads about as fast as the rotation consumes)
+  const int nthreads = std::max(1, std::min(4, depth / 2));
+  for (int k = 0; k < nthreads; ++k) r->readers.emplace_back(reader_main, r);
   *out = r;
   return ok();
 }
@@ -152,15 +165,23 @@ clak_status clak_bed_scan(clak_bed_t r, clak_plan_t h, void* d_b, void* d_se, in
   if (ldo < r->m) return fail(CLAK_E_ARG, "bed_scan: ldo=%lld < m=%lld", (long long)ldo, (long long)r->m);
   if (!d_b || !d_se) return fail(CLAK_E_ARG, "bed_scan: null b or se");
   {
+    // a finished scan rewinds the reader: the next one reads the file again from the start
     std::lock_guard<std::mutex> lk(r->mu);
-    if (r->released != 0 || !r->err.empty())
-      return fail(CLAK_E_STATE, "bed_scan: a reader serves one scan (open the file again)");
+    if (!r->err.empty()) return fail(CLAK_E_ARG, "bed_scan: %s", r->err.c_str());
+    if (r->released == r->nblocks) {
+      r->claimed = 0;
+      r->released = 0;
+      for (auto& h : r->holds) h = -1;
+      r->cv.notify_all();
+    } else if (r->released != 0) {
+      return fail(CLAK_E_STATE, "bed_scan: an earlier scan of this reader did not finish (open the file again)");
+    }
   }
   const size_t esz = out_dtype == CLAK_OUT_F64 ? 8 : 4;
   const int64_t pw = (p->flags & CLAK_OUT_FULL) ? p->pL + 1 : 1;
   auto get = [&](int64_t b, clak_block* B) -> clak_status {
     std::unique_lock<std::mutex> lk(r->mu);
-    r->cv.wait(lk, [&] { return r->produced > b || !r->err.empty(); });
+    r->cv.wait(lk, [&] { return r->holds[b % r->depth] == b || !r->err.empty(); });
     if (!r->err.empty()) return fail(CLAK_E_ARG, "bed_scan: %s", r->err.c_str());
     const int64_t first = b * r->block;
     B->m_blk = std::min(r->block, r->m - first);
@@ -178,6 +199,7 @@ clak_status clak_bed_scan(clak_bed_t r, clak_plan_t h, void* d_b, void* d_se, in
     if (hipEventRecord(r->freed[k], s_in) != hipSuccess) return fail(CLAK_E_DEVICE, "bed_scan: hipEventRecord");
     std::lock_guard<std::mutex> lk(r->mu);
     r->armed[k] = 1;
+    r->holds[k] = -1;
     r->released = b + 1;
     r->cv.notify_all();
     return CLAK_OK;

@@ -90,13 +90,12 @@ def test_bed_scan_matches_blocks_and_oracle(tmp_path, prec, full, depth):
         h = clak.clak_bed_open(str(path), w.n, w.m, block, depth)
         try:
             clak.clak_bed_scan(h, plan.handle, *out)
-            with pytest.raises(clak.ClakError) as e:
-                clak.clak_bed_scan(h, plan.handle, *out)
-            assert e.value.status == clak.CLAK_E_STATE
+            again = _outs(w, w.m, torch.float32, full)  # a finished scan rewinds the reader
+            clak.clak_bed_scan(h, plan.handle, *again)
         finally:
             clak.clak_bed_close(h)
-        for a, r in zip(out, ref):
-            assert _same(a, r)
+        for a, a2, r in zip(out, again, ref):
+            assert _same(a, r) and _same(a2, r)
     # parity of the scanned genotypes with the oracle's own reading of the file, on sampled cells
     gf = obed.read_bed(path, w.n, w.m)
     rng = np.random.default_rng(3)
@@ -137,3 +136,29 @@ def test_bed_scan_argument_errors(tmp_path):
             assert bool(torch.isfinite(pv).all()) and int(fl.max()) == 0
         finally:
             clak.clak_bed_close(h)
+
+
+def test_staging_contiguous_and_wide_rows():
+    """CLAK_STAGE_GENOTYPES moves rows that fit the staging pitch as one contiguous copy and re-pitches
+    wider ones; both give the unstaged results bitwise (u8 rows 3n + 5 wide, f16 rows, 2-bit rows)."""
+    import torch
+
+    from paper_1207_2169_amd import clak
+    w = make_workload(2, n=250, m=300, t=3, kin_cols=500)
+    g = w.genotypes(0, w.m)
+    wide = np.zeros((w.m, 3 * w.n + 5), np.uint8)
+    wide[:, :w.n] = g
+    print("staging wide rows", flush=True)
+    with _plan(w, 1, w.m) as plan:
+        ref = _outs(w, w.m, torch.float64)
+        clak.clak_run_block(plan.handle, torch.from_numpy(g).cuda(), *ref)
+        torch.cuda.synchronize()
+    cases = [(torch.from_numpy(wide).cuda(), None), (torch.from_numpy(wide).pin_memory(), None),
+             (torch.from_numpy(g).half().cuda(), None), (torch.from_numpy(pack_rows(g)).pin_memory(), clak.CLAK_G_P2)]
+    with _plan(w, 1, w.m, clak.CLAK_STAGE_GENOTYPES) as plan:
+        for G, gdt in cases:
+            out = _outs(w, w.m, torch.float64)
+            clak.clak_run_block(plan.handle, G, *out, g_dtype=gdt)
+            torch.cuda.synchronize()
+            for a, r in zip(out, ref):
+                assert _same(a, r)
