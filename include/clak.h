@@ -331,7 +331,11 @@ clak_status clak_bed_close(clak_bed_t bed);
 
 /* Turns per-stage timing on (enable != 0) or off and clears the
  * accumulators.  While on, clak_run_block brackets each stage's kernel with
- * HIP events on the plan's stream (a little host overhead per launch). */
+ * HIP events on the stream it runs on (a little host overhead per launch),
+ * and pipelines, batches and file scans run the compute kernels of
+ * consecutive blocks on one stream, so that no two of them overlap and each
+ * bracketed time is that kernel's own (the ingest still overlaps on its side
+ * stream). */
 clak_status clak_plan_set_profiling(clak_plan_t plan, int enable);
 
 /* Waits for the plan's stream, then returns per stage the summed kernel time

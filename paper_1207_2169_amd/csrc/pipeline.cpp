@@ -8,7 +8,8 @@
 // so the memory-bound ingest overlaps the MFMA-bound rotation.  Each slot has
 // its own compute stream, so the kernels of block b + 1 start while the last
 // work-groups of block b drain (every buffer a block writes belongs to its
-// slot or to its own outputs).  A launch enqueues the whole schedule from the host: the side and
+// slot or to its own outputs); with the stage profiler on, one compute stream
+// serves both slots so that per-kernel times are not shared.  A launch enqueues the whole schedule from the host: the side and
 // main streams are forked from the launch stream by an event and joined back
 // to it at the end, so the launch stream sees the pipeline as one unit of work.
 // Cohorts of a batch get their own stream pairs and run concurrently.
@@ -56,6 +57,13 @@ void release(Schedule* g) {
   delete g;
 }
 
+// The compute stream of a slot.  While the stage profiler runs, both slots
+// share one, so that each kernel's bracketed time is its own (consecutive
+// blocks do not overlap); the ingest still overlaps on its side stream.
+hipStream_t compute_stream(const Plan* p, const PlanStreams& c, int slot) {
+  return p->profiling ? c.s_main[0] : c.s_main[slot];
+}
+
 #define CK(expr, what)                                                                      \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
@@ -91,20 +99,23 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
   CK(hipEventRecord(g->fork, origin), what);
   for (auto& c : g->ps) {
     Plan* p = c.plan;
-    for (int q = 0; q < NSLOTS; ++q) CK(hipStreamWaitEvent(c.s_main[q], g->fork, 0), what);
+    // compute streams this launch uses (one for a single block or while profiling)
+    const int nmain = (p->profiling || c.count < 2) ? 1 : NSLOTS;
+    for (int q = 0; q < nmain; ++q) CK(hipStreamWaitEvent(c.s_main[q], g->fork, 0), what);
     CK(hipStreamWaitEvent(c.s_in, g->fork, 0), what);
     for (int64_t j = 0; j < c.count; ++j) {
       const int slot = (int)(j % NSLOTS);
+      const hipStream_t sm = compute_stream(p, c, slot);
       if (j >= NSLOTS) CK(hipStreamWaitEvent(c.s_in, c.done[slot], 0), what);
       const clak_block& B = g->blocks[c.first + j];
-      clak_status st = enqueue_block(p, slot, c.s_in, c.s_main[slot], c.ingested[slot], B.m_blk, B.G, g->g_dtype,
+      clak_status st = enqueue_block(p, slot, c.s_in, sm, c.ingested[slot], B.m_blk, B.G, g->g_dtype,
                                      B.ldg, cell_out(B.b, B.se, B.pval, B.flags, B.ldo, g->out_dtype));
       if (st) return st;
-      CK(hipEventRecord(c.done[slot], c.s_main[slot]), what);
+      CK(hipEventRecord(c.done[slot], sm), what);
     }
     CK(hipEventRecord(c.joined_in, c.s_in), what);
     CK(hipStreamWaitEvent(origin, c.joined_in, 0), what);
-    for (int q = 0; q < NSLOTS; ++q) {
+    for (int q = 0; q < nmain; ++q) {
       CK(hipEventRecord(c.joined_main[q], c.s_main[q]), what);
       CK(hipStreamWaitEvent(origin, c.joined_main[q], 0), what);
     }
@@ -157,11 +168,12 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
     if ((result = get(j, &B))) break;
     if ((result = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval))) break;
     if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(c.s_in, c.done[slot], 0)))) break;
-    if ((result = enqueue_block(p, slot, c.s_in, c.s_main[slot], c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
+    const hipStream_t sm = compute_stream(p, c, slot);
+    if ((result = enqueue_block(p, slot, c.s_in, sm, c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
                                 cell_out(B.b, B.se, B.pval, B.flags, B.ldo, out_dtype))))
       break;
     if ((result = after(j, c.s_in))) break;
-    result = ck(hipEventRecord(c.done[slot], c.s_main[slot]));
+    result = ck(hipEventRecord(c.done[slot], sm));
   }
   // join everything enqueued so far back to the plan's stream and wait for it
   clak_status js = ck(hipEventRecord(c.joined_in, c.s_in));
