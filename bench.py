@@ -249,7 +249,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the grid shards over SNP blocks and "
-              "trait groups with one broadcast of Z, which this build does not launch", file=sys.stderr)
+              "trait groups with one broadcast of Z; only the one-GPU shard is implemented and measured here", file=sys.stderr)
         sys.exit(2)
     import torch
 
