@@ -49,3 +49,9 @@ def test_host_only_calls_without_a_gpu():
     h = ctypes.c_void_p()
     assert lib.clak_plan_create(ctypes.byref(h), 10, 3, 2, 10, 0, clak.CLAK_CHOL) == clak.CLAK_E_ARG
     assert b"t = 1" in lib.clak_last_error()
+    # sizes outside what a precision supports are refused before any device work
+    assert lib.clak_plan_create(ctypes.byref(h), 40000, 3, 1, 10, clak.CLAK_PREC_MIXED, 0) == clak.CLAK_E_UNSUPPORTED
+    assert lib.clak_plan_create(ctypes.byref(h), 100, 9, 1, 10, clak.CLAK_PREC_MIXED, 0) == clak.CLAK_E_UNSUPPORTED
+    assert lib.clak_plan_create(ctypes.byref(h), 100, 17, 1, 10, clak.CLAK_PREC_FP64, 0) == clak.CLAK_E_ARG
+    assert lib.clak_plan_create(ctypes.byref(h), 3, 3, 1, 10, clak.CLAK_PREC_FP64, 0) == clak.CLAK_E_ARG
+    assert lib.clak_plan_create(ctypes.byref(h), 100, 3, 1, 10, 0, 1 << 5) == clak.CLAK_E_ARG
