@@ -171,7 +171,7 @@ clak_status clak_bed_scan(clak_bed_t r, clak_plan_t h, void* d_b, void* d_se, in
     if (r->released == r->nblocks) {
       r->claimed = 0;
       r->released = 0;
-      for (auto& h : r->holds) h = -1;
+      for (auto& held : r->holds) held = -1;
       r->cv.notify_all();
     } else if (r->released != 0) {
       return fail(CLAK_E_STATE, "bed_scan: an earlier scan of this reader did not finish (open the file again)");
