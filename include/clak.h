@@ -269,7 +269,10 @@ clak_status clak_batch_destroy(clak_batch_t batch);
 /* Launch parameters of the mixed path's kernels, all of which leave every
  * result bitwise unchanged (they only change how tiles map to work-groups):
  *   rot_cfg : the rotation's tile configuration, 64-row tiles of 64, 128 or
- *             256 SNPs with two, four or eight waves (0 to 4);
+ *             256 SNPs with two, four or eight waves (1 to 9; 6 to 9, like
+ *             the built-in choice, stage their operands by direct
+ *             global-to-LDS loads into a ring of three or four K slices, 1
+ *             to 5 through registers, one slice ahead);
  *   rot_rg  : the rotation's XCD row groups (1, 2, 4, 8; the 8 XCDs split into
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
  *   grid_tt : traits per work-group of the grid contraction (32 or 64);
@@ -332,10 +335,9 @@ clak_status clak_bed_close(clak_bed_t bed);
 /* Turns per-stage timing on (enable != 0) or off and clears the
  * accumulators.  While on, clak_run_block brackets each stage's kernel with
  * HIP events on the stream it runs on (a little host overhead per launch),
- * and pipelines, batches and file scans run the compute kernels of
- * consecutive blocks on one stream, so that no two of them overlap and each
- * bracketed time is that kernel's own (the ingest still overlaps on its side
- * stream). */
+ * and pipelines, batches and file scans run every kernel of consecutive
+ * blocks, the ingest included, on one stream, so that no two of them overlap
+ * and each bracketed time is that kernel's own. */
 clak_status clak_plan_set_profiling(clak_plan_t plan, int enable);
 
 /* Waits for the plan's stream, then returns per stage the summed kernel time

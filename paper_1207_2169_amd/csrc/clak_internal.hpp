@@ -19,7 +19,7 @@ namespace clak {
 constexpr int64_t KPAD = 128;
 constexpr int64_t SNP_PAD = 256;  // multiple of every SNP tile width
 constexpr int64_t TRAIT_PAD = 128;
-constexpr int ROT_CONFIGS = 5;  // tile configurations of the mixed rotation (tunable)
+constexpr int ROT_CONFIGS = 10;  // tile configurations of the mixed rotation (tunable)
 constexpr int MAX_PL = 16;
 constexpr int ING_MAX_SPLITS = 8;  // individual windows of the ingest are split over at most this many work-groups
 // int8 digit encoding: a value v with |v| <= s is stored as

@@ -31,7 +31,9 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 // digit planes of Z^T for them (v_mfma_i32_32x32x32_i8), so one genotype
 // fragment feeds four MFMAs.  The K loop runs over 64-deep slices with LDS
 // double buffering (one barrier per slice; the next slice's global loads are
-// in flight during the current slice's MFMAs).  Work-groups are dispatched
+// in flight during the current slice's MFMAs), or (DL) a ring of three or
+// four slots filled by direct global-to-LDS loads (the next two or three
+// slices in flight).  Work-groups are dispatched
 // round-robin over the 8 XCDs; the tiles are laid out as an rg x (8 / rg)
 // grid of (row group, SNP group) so that XCD x owns 1 / rg of the Z^T rows
 // (which stay in its L2) for rg / 8 of the SNP tiles, walking each SNP tile
@@ -62,7 +64,26 @@ constexpr int rot_waves() {
   return CT == 1 ? (PL <= 4 ? 3 : 2) : ((CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2);
 }
 
-template <int PL, int EPI, int CT, int WR, int WC>
+// Encoded s_waitcnt immediate that waits until at most N vector memory
+// operations of the wave are outstanding (expcnt and lgkmcnt not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Work-group barrier for the direct-load ring: the wave's LDS reads complete
+// (lgkmcnt 0), then s_barrier.  Unlike __syncthreads it does not wait for
+// the wave's outstanding global-to-LDS loads; the caller waits for the ones
+// it needs (wait_vm) before the barrier.  The memory clobbers keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+template <int PL, int EPI, int CT, int WR, int WC, int DL>
 __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri, const int8_t* __restrict__ Zd,
              const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
@@ -72,7 +93,17 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   constexpr int A_STAGE = 4 * BM * LROW, B_STAGE = BN * LROW;
   constexpr int A_LD = 16 * BM / NT, B_LD = 4 * BN / NT;  // 16-byte loads per thread per slice
   static_assert(16 * BM % NT == 0 && 4 * BN % NT == 0, "tile / thread mismatch");
-  __shared__ __attribute__((aligned(16))) int8_t smem[2 * (A_STAGE + B_STAGE)];
+  // DL: stages of whole 1 KB MFMA fragments (32 rows x 32 bytes of K), FA of
+  // Z^T (plane, row block, K half) then FB of the genotypes (column block, K
+  // half), written by direct global-to-LDS loads into a ring of DL (3 or 4)
+  // slots, each its own LDS array so that the compiler can tell them apart
+  static_assert(DL == 0 || DL == 3 || DL == 4, "ring depth");
+  constexpr int FA = 8 * WR, FB = 2 * CT * WC, FS = FA + FB;
+  constexpr int SMEM = DL ? FS * 1024 : 2 * (A_STAGE + B_STAGE);
+  __shared__ __attribute__((aligned(1024))) int8_t smem[SMEM];
+  __shared__ __attribute__((aligned(1024))) int8_t smem1[DL ? FS * 1024 : 16];
+  __shared__ __attribute__((aligned(1024))) int8_t smem2[DL ? FS * 1024 : 16];
+  __shared__ __attribute__((aligned(1024))) int8_t smem3[DL == 4 ? FS * 1024 : 16];
   // epilogue tables, fetched while the first stage loads
   constexpr int NTAB = BM * PL + BM + BN * PL + (EPI == 1 ? BM * NP : 0);
   __shared__ double tab[NTAB];
@@ -105,42 +136,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   // (plane, 32-row block, half of the 64-byte slice); lane l of a group takes
   // row l % 32, chunk l / 32 of that half, the lane pattern of the fragment
   // reads, so the LDS stores are free of bank conflicts.
-  v4i ra[A_LD], rb[B_LD];
-  const int srow = lane & 31, sch = lane >> 5;
-  auto gload = [&](int kt) {
-    const int64_t k0 = (int64_t)kt * BK;
-#pragma unroll
-    for (int q = 0; q < A_LD; ++q) {  // group (tid + NT q) / 64: half g % 2, row block (g / 2) % (BM / 32), plane
-      const int g = (tid + NT * q) >> 6;
-      const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
-      ra[q] = *(const v4i*)(Zd + pl * zplane + kt32(m0 + 32 * rb32 + srow, k0 + 32 * kh, np) + 16 * sch);
-    }
-#pragma unroll
-    for (int q = 0; q < B_LD; ++q) {
-      const int g = (tid + NT * q) >> 6;
-      const int kh = g & 1, rb32 = g >> 1;
-      rb[q] = *(const v4i*)(Gp + kt32(n0 + 32 * rb32 + srow, k0 + 32 * kh, mbp) + 16 * sch);
-    }
-  };
-  auto lstore = [&](int buf) {
-    int8_t* As = smem + buf * A_STAGE;
-    int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
-#pragma unroll
-    for (int q = 0; q < A_LD; ++q) {
-      const int g = (tid + NT * q) >> 6;
-      const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
-      *(v4i*)(As + (pl * BM + 32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = ra[q];
-    }
-#pragma unroll
-    for (int q = 0; q < B_LD; ++q) {
-      const int g = (tid + NT * q) >> 6;
-      const int kh = g & 1, rb32 = g >> 1;
-      *(v4i*)(Bs + (32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = rb[q];
-    }
-  };
-
-  gload(0);
-  {
+  auto load_tables = [&]() {
     const int64_t ss = snp_stride(PL);
     for (int e = tid; e < BM * PL; e += NT) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
     for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
@@ -150,33 +146,155 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
         const int r = e / NP, q = e % NP;
         Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
       }
-  }
-  lstore(0);
-  __syncthreads();
-  if (KT > 1) gload(1);
-  for (int kt = 0; kt < KT; ++kt) {
-    const int buf = kt & 1;
-    const int8_t* As = smem + buf * A_STAGE;
-    const int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
+  };
+
+  if constexpr (DL) {
+    // Each wave moves FS / (WR WC) fragments per stage; lane l fetches bytes
+    // [16 (l / 32), +16) of row l % 32 of its fragment, which the load writes
+    // to byte 16 l of the fragment's LDS slot, the order of the MFMA operand
+    // reads (conflict-free, contiguous).  The loads of the next DL - 1 K
+    // slices are in flight while one is multiplied.
+    constexpr int NW = WR * WC, LPW = FS / NW, LPA = FA / NW;
+    static_assert(FA % NW == 0 && FB % NW == 0 && LPW < 32, "fragments per wave");
+    const int w = __builtin_amdgcn_readfirstlane(wid);
+    const int loff = 32 * (lane & 31) + 16 * (lane >> 5);
+    // fragment q of this wave is fi = q NW + w: Z^T fragments for q < LPA
+    const int8_t* za = Zd + m0 * 32 + loff;
+    const int8_t* gb = Gp + n0 * 32 + loff;
+    auto slot = [&](auto u) -> int8_t* {
+      if constexpr (decltype(u)::value == 0) return smem;
+      else if constexpr (decltype(u)::value == 1) return smem1;
+      else if constexpr (decltype(u)::value == 2) return smem2;
+      else return smem3;
+    };
+    auto issue = [&](auto u, int kt) {
+      int8_t* st = slot(u);
+      const int64_t s0 = 2 * (int64_t)kt;  // first 32-byte K slice of the stage
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
-      v4i b[CT], a[4];
+      for (int q = 0; q < LPW; ++q) {
+        const int fi = q * NW + w;
+        const int8_t* src;
+        if (q < LPA) {
+          const int h = fi & 1, r = (fi >> 1) % WR, pl = (fi >> 1) / WR;
+          src = za + pl * zplane + ((s0 + h) * np + 32 * r) * 32;
+        } else {
+          const int h = (fi - FA) & 1, c = (fi - FA) >> 1;
+          src = gb + ((s0 + h) * mbp + 32 * c) * 32;
+        }
+        __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(st + fi * 1024), 16, 0, 0);
+      }
+    };
+    // Slice kt sits in slot kt % DL.  Every step has the same shape, so the
+    // outstanding loads are the same on every path into a step: wait until
+    // this wave's loads of slice kt have landed (only those of the next DL - 2
+    // slices remain), barrier (every wave's loads of kt are in; every wave is
+    // done reading slice kt - 1), load slice kt + DL - 1 into the slot kt - 1
+    // used, multiply slice kt.  Past the last slice the load repeats slice
+    // KT - 1 into a slot that is not read again; it stays in bounds.
+    auto step = [&](auto u, int kt) {
+      wait_vm<(DL - 2) * LPW>();
+      lds_barrier();
+      issue(std::integral_constant<int, (decltype(u)::value + DL - 1) % DL>{}, min(kt + DL - 1, KT - 1));
+      const int8_t* st = slot(u) + 16 * lane;
 #pragma unroll
-      for (int ct = 0; ct < CT; ++ct)
-        b[ct] = *(const v4i*)(Bs + (32 * (CT * wc + ct) + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
+      for (int ks = 0; ks < 2; ++ks) {
+        v4i b[CT], a[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
-        a[p] = *(const v4i*)(As + (p * BM + 32 * wr + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
+        for (int ct = 0; ct < CT; ++ct) b[ct] = *(const v4i*)(st + (FA + 2 * (CT * wc + ct) + ks) * 1024);
 #pragma unroll
-      for (int p = 0; p < 4; ++p)
+        for (int p = 0; p < 4; ++p) a[p] = *(const v4i*)(st + (2 * (p * WR + wr) + ks) * 1024);
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[p], b[ct], acc[ct][p]);
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[p], b[ct], acc[ct][p]);
+      }
+    };
+    using U0 = std::integral_constant<int, 0>;
+    using U1 = std::integral_constant<int, 1>;
+    using U2 = std::integral_constant<int, 2>;
+    using U3 = std::integral_constant<int, 3>;
+    issue(U0{}, 0);
+    load_tables();
+    issue(U1{}, min(1, KT - 1));
+    if constexpr (DL == 4) issue(U2{}, min(2, KT - 1));
+    int kt = 0;
+    for (; kt + DL <= KT; kt += DL) {
+      step(U0{}, kt);
+      step(U1{}, kt + 1);
+      step(U2{}, kt + 2);
+      if constexpr (DL == 4) step(U3{}, kt + 3);
     }
-    if (kt + 1 < KT) {
-      lstore(buf ^ 1);
-      if (kt + 2 < KT) gload(kt + 2);
-    }
+    if (kt < KT) step(U0{}, kt);
+    if (kt + 1 < KT) step(U1{}, kt + 1);
+    if constexpr (DL == 4)
+      if (kt + 2 < KT) step(U2{}, kt + 2);
+    wait_vm<0>();  // no load is left in flight
+    __syncthreads();  // the epilogue reuses the ring
+  } else {
+    v4i ra[A_LD], rb[B_LD];
+    const int srow = lane & 31, sch = lane >> 5;
+    auto gload = [&](int kt) {
+      const int64_t k0 = (int64_t)kt * BK;
+  #pragma unroll
+      for (int q = 0; q < A_LD; ++q) {  // group (tid + NT q) / 64: half g % 2, row block (g / 2) % (BM / 32), plane
+        const int g = (tid + NT * q) >> 6;
+        const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
+        ra[q] = *(const v4i*)(Zd + pl * zplane + kt32(m0 + 32 * rb32 + srow, k0 + 32 * kh, np) + 16 * sch);
+      }
+  #pragma unroll
+      for (int q = 0; q < B_LD; ++q) {
+        const int g = (tid + NT * q) >> 6;
+        const int kh = g & 1, rb32 = g >> 1;
+        rb[q] = *(const v4i*)(Gp + kt32(n0 + 32 * rb32 + srow, k0 + 32 * kh, mbp) + 16 * sch);
+      }
+    };
+    auto lstore = [&](int buf) {
+      int8_t* As = smem + buf * A_STAGE;
+      int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
+  #pragma unroll
+      for (int q = 0; q < A_LD; ++q) {
+        const int g = (tid + NT * q) >> 6;
+        const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
+        *(v4i*)(As + (pl * BM + 32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = ra[q];
+      }
+  #pragma unroll
+      for (int q = 0; q < B_LD; ++q) {
+        const int g = (tid + NT * q) >> 6;
+        const int kh = g & 1, rb32 = g >> 1;
+        *(v4i*)(Bs + (32 * rb32 + srow) * LROW + 16 * (2 * kh + sch)) = rb[q];
+      }
+    };
+
+    gload(0);
+    load_tables();
+    lstore(0);
     __syncthreads();
+    if (KT > 1) gload(1);
+    for (int kt = 0; kt < KT; ++kt) {
+      const int buf = kt & 1;
+      const int8_t* As = smem + buf * A_STAGE;
+      const int8_t* Bs = smem + 2 * A_STAGE + buf * B_STAGE;
+  #pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        v4i b[CT], a[4];
+  #pragma unroll
+        for (int ct = 0; ct < CT; ++ct)
+          b[ct] = *(const v4i*)(Bs + (32 * (CT * wc + ct) + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
+  #pragma unroll
+        for (int p = 0; p < 4; ++p)
+          a[p] = *(const v4i*)(As + (p * BM + 32 * wr + (lane & 31)) * LROW + 16 * (lane >> 5) + 32 * ks);
+  #pragma unroll
+        for (int p = 0; p < 4; ++p)
+  #pragma unroll
+          for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[p], b[ct], acc[ct][p]);
+      }
+      if (kt + 1 < KT) {
+        lstore(buf ^ 1);
+        if (kt + 2 < KT) gload(kt + 2);
+      }
+      __syncthreads();
+    }
+
   }
 
   // pair the four digit-plane sums exactly in int32 (|sum| < 2^23 for
@@ -195,9 +313,11 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   static_assert(WR * BN * NP * 8 <= 2 * (A_STAGE + B_STAGE), "LDS reuse");
   const int64_t ss = snp_stride(PL);
 
-  // one column tile at a time
+  // one column tile at a time (the scheduler is kept from overlapping the
+  // tiles' table reads, which would not fit the registers)
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
+    __builtin_amdgcn_sched_barrier(0);
     const int cl = 32 * (CT * wc + ct) + (lane & 31);
     const int64_t col = n0 + cl;
     double v[PL];
@@ -224,6 +344,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
 #pragma unroll
           for (int q = 0; q <= PL; ++q) ps[q] += Vs[rr * NP + q] * x;
           ps[PL + 1] += Vs[rr * NP + PL + 1] * x * x;
+          __builtin_amdgcn_sched_barrier(0);  // one row's table reads live at a time
         }
       }
       if (EPI == 0) *(v4d*)(X + col * np + m0 + rb0) = (v4d){xs[0], xs[1], xs[2], xs[3]};
@@ -255,18 +376,27 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   }
 }
 
-// Rotation tile configuration: CT 32-column MFMA tiles per wave, WR x WC waves.
-// Rotation tile configurations (CT, WR, WC), all with 64-row tiles so that the
-// single-trait partials (one per 64-row tile, combined over the WR = 2 wave
-// rows in a fixed order) are bitwise the same whichever is chosen:
-//   0: 2, 2, 2   64 x 128 tile, 4 waves (two work-groups per CU)
-//   1: 4, 2, 1   64 x 128 tile, 2 waves, four column tiles per wave
-//   2: 2, 2, 4   64 x 256 tile, 8 waves
-//   3: 4, 2, 2   64 x 256 tile, 4 waves, four column tiles per wave
-//   4: 1, 2, 2   64 x 64 tile, 4 waves, one column tile per wave (three
-//                work-groups per CU: more loads in flight per CU)
+// Rotation tile configurations (CT 32-column MFMA tiles per wave, WR x WC
+// waves; DL: staged by direct global-to-LDS loads into a ring of three (DL3)
+// or four (DL4) K slices, two or three slices in flight and no staging
+// registers or LDS stores issued by the waves, else through registers one
+// slice ahead), all with 64-row
+// tiles so that the single-trait partials (one per 64-row tile, combined over
+// the WR = 2 wave rows in a fixed order) are bitwise the same whichever is
+// chosen:
+//   0: 2, 2, 2, DL3 64 x 128 tile, 4 waves (two work-groups per CU); built-in
+//   1: 4, 2, 1      64 x 128 tile, 2 waves, four column tiles per wave
+//   2: 2, 2, 4      64 x 256 tile, 8 waves
+//   3: 4, 2, 2      64 x 256 tile, 4 waves, four column tiles per wave
+//   4: 1, 2, 2      64 x 64 tile, 4 waves, one column tile per wave (three
+//                   work-groups per CU: more loads in flight per CU)
+//   5: 2, 2, 2      as 0, register-staged
+//   6: 2, 2, 4, DL3 as 2, direct loads (one work-group per CU)
+//   7: 1, 2, 2, DL3 as 4, direct loads
+//   8: 2, 2, 4, DL4 as 6, three slices in flight
+//   9: 2, 2, 2, DL4 as 0, three slices in flight (one work-group per CU)
 constexpr int ROT_BM = 64;
-static_assert(ROT_CONFIGS == 5, "rotation configurations");
+static_assert(ROT_CONFIGS == 10, "rotation configurations");
 static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0, "rotation tiles must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
@@ -327,7 +457,7 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
   for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + off) = pk[q];
 }
 
-template <int CT, int WR, int WC>
+template <int CT, int WR, int WC, int DL>
 static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   constexpr int BN = 32 * CT * WC;
   static_assert(32 * WR == ROT_BM && SNP_PAD % BN == 0, "rotation tile");
@@ -340,7 +470,7 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   dim3 block(64 * WR * WC);
 #define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                         \
   case PLV:                                                                                                        \
-    k_rot_i8<PLV, EPI, CT, WR, WC><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd,      \
+    k_rot_i8<PLV, EPI, CT, WR, WC, DL><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd,  \
                                                                  W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);       \
     break;
   if (p.fused_t1) {
@@ -367,15 +497,25 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   switch (p.rot_cfg) {
     case 1:
-      return rotate_cfg<4, 2, 1>(p, m_blk);
+      return rotate_cfg<4, 2, 1, 0>(p, m_blk);
     case 2:
-      return rotate_cfg<2, 2, 4>(p, m_blk);
+      return rotate_cfg<2, 2, 4, 0>(p, m_blk);
     case 3:
-      return rotate_cfg<4, 2, 2>(p, m_blk);
+      return rotate_cfg<4, 2, 2, 0>(p, m_blk);
     case 4:
-      return rotate_cfg<1, 2, 2>(p, m_blk);
+      return rotate_cfg<1, 2, 2, 0>(p, m_blk);
+    case 5:
+      return rotate_cfg<2, 2, 2, 0>(p, m_blk);
+    case 6:
+      return rotate_cfg<2, 2, 4, 3>(p, m_blk);
+    case 7:
+      return rotate_cfg<1, 2, 2, 3>(p, m_blk);
+    case 8:
+      return rotate_cfg<2, 2, 4, 4>(p, m_blk);
+    case 9:
+      return rotate_cfg<2, 2, 2, 4>(p, m_blk);
     default:
-      return rotate_cfg<2, 2, 2>(p, m_blk);
+      return rotate_cfg<2, 2, 2, 3>(p, m_blk);
   }
 }
 

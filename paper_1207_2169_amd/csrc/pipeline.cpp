@@ -106,9 +106,12 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
     for (int64_t j = 0; j < c.count; ++j) {
       const int slot = (int)(j % NSLOTS);
       const hipStream_t sm = compute_stream(p, c, slot);
-      if (j >= NSLOTS) CK(hipStreamWaitEvent(c.s_in, c.done[slot], 0), what);
+      // while profiling the ingest runs on the compute stream too, so that
+      // every stage is timed without a concurrent kernel
+      const hipStream_t si = p->profiling ? sm : c.s_in;
+      if (j >= NSLOTS) CK(hipStreamWaitEvent(si, c.done[slot], 0), what);
       const clak_block& B = g->blocks[c.first + j];
-      clak_status st = enqueue_block(p, slot, c.s_in, sm, c.ingested[slot], B.m_blk, B.G, g->g_dtype,
+      clak_status st = enqueue_block(p, slot, si, sm, c.ingested[slot], B.m_blk, B.G, g->g_dtype,
                                      B.ldg, cell_out(B.b, B.se, B.pval, B.flags, B.ldo, g->out_dtype));
       if (st) return st;
       CK(hipEventRecord(c.done[slot], sm), what);
@@ -167,12 +170,13 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
     clak_block B{};
     if ((result = get(j, &B))) break;
     if ((result = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval))) break;
-    if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(c.s_in, c.done[slot], 0)))) break;
     const hipStream_t sm = compute_stream(p, c, slot);
-    if ((result = enqueue_block(p, slot, c.s_in, sm, c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
+    const hipStream_t si = p->profiling ? sm : c.s_in;  // as in run_schedule
+    if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(si, c.done[slot], 0)))) break;
+    if ((result = enqueue_block(p, slot, si, sm, c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
                                 cell_out(B.b, B.se, B.pval, B.flags, B.ldo, out_dtype))))
       break;
-    if ((result = after(j, c.s_in))) break;
+    if ((result = after(j, si))) break;
     result = ck(hipEventRecord(c.done[slot], sm));
   }
   // join everything enqueued so far back to the plan's stream and wait for it

@@ -9,11 +9,11 @@ from synth import make_workload
 pytestmark = pytest.mark.gpu
 
 
-def _plan(w, block):
+def _plan(w, block, flags=0):
     import torch
 
     from paper_1207_2169_amd import clak
-    plan = clak.Plan(w.n, w.pL, w.t, block, clak.CLAK_PREC_MIXED)
+    plan = clak.Plan(w.n, w.pL, w.t, block, clak.CLAK_PREC_MIXED, flags)
     clak.clak_set_kinship(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Phi)).cuda())
     clak.clak_set_covariates(plan.handle, torch.from_numpy(np.ascontiguousarray(w.XL.T)).cuda().t())
     clak.clak_set_traits(plan.handle, torch.from_numpy(np.ascontiguousarray(w.Y.T)).cuda().t(),
@@ -27,20 +27,24 @@ def _outputs(w):
     return b, torch.full_like(b, float("nan")), torch.full((w.t, w.m), 255, dtype=torch.uint8, device="cuda")
 
 
-@pytest.mark.parametrize("t", [1, 150])
-def test_every_tuning_is_bitwise_identical(t):
+# n_pad = 256, 384, 512: 4, 6 and 8 K slices of 64 (every remainder of the
+# three-slot ring of the direct-load rotations); CLAK-Chol rotates triangular
+# tiles of 1 to n_pad / 64 slices
+@pytest.mark.parametrize("t,n,chol", [(1, 300, False), (150, 300, False), (1, 200, False), (1, 450, False),
+                                      (1, 450, True)])
+def test_every_tuning_is_bitwise_identical(t, n, chol):
     import torch
 
     from paper_1207_2169_amd import clak
-    w = make_workload(2, n=300, m=700, t=t, kin_cols=600)
-    print(f"tuning sweep t={t}", flush=True)
+    w = make_workload(2, n=n, m=700, t=t, kin_cols=2 * n)
+    print(f"tuning sweep t={t} n={n} chol={chol}", flush=True)
     G = torch.from_numpy(w.genotypes(0, w.m)).cuda()
-    with _plan(w, w.m) as plan:
+    with _plan(w, w.m, clak.CLAK_CHOL if chol else 0) as plan:
         ref = _outputs(w)
         clak.clak_run_block(plan.handle, G, *ref)
         torch.cuda.synchronize()
         assert bool(torch.isfinite(ref[0]).all()) and bool((ref[2] == 0).all())
-        for cfg in (0, 1, 2, 3, 4):
+        for cfg in range(10):
             for rg in (1, 2, 4, 8):
                 for tt in ((32, 64) if t > 1 else (0,)):
                     for xt in ((1, 2, 4, 8) if t > 1 else (0,)):
@@ -70,7 +74,7 @@ def test_autotune_matches_run_block_and_uses_cache(tmp_path):
             assert torch.equal(a, r)
         tuned = clak.clak_plan_get_tuning(plan.handle)
         # 0 keeps the built-in choice (no candidate more than 3 % faster)
-        assert tuned[0] in (0, 1, 2, 3, 4) and tuned[1] in (0, 1, 2, 4, 8) and tuned[2] in (0, 32, 64)
+        assert tuned[0] in range(10) and tuned[1] in (0, 1, 2, 4, 8) and tuned[2] in (0, 32, 64)
         assert tuned[3] in (0, 1, 2, 4, 8)
         lines = cache.read_text().splitlines()
         assert len(lines) == 1 and lines[0].startswith("gfx950 n_pad=384 p_L=3 t=100 m_blk=1000 ")
