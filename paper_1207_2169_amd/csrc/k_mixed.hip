@@ -191,23 +191,37 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     // done reading slice kt - 1), load slice kt + DL - 1 into the slot kt - 1
     // used, multiply slice kt.  Past the last slice the load repeats slice
     // KT - 1 into a slot that is not read again; it stays in bounds.
+    // Within a step, the fragments of both 32-deep halves are read first (the
+    // first MFMAs then wait for the LDS only once), and the next slice's
+    // direct loads are spread over the MFMAs.
     auto step = [&](auto u, int kt) {
       wait_vm<(DL - 2) * LPW>();
       lds_barrier();
-      issue(std::integral_constant<int, (decltype(u)::value + DL - 1) % DL>{}, min(kt + DL - 1, KT - 1));
       const int8_t* st = slot(u) + 16 * lane;
+      v4i b[2][CT], a[2][4];
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
-        v4i b[CT], a[4];
 #pragma unroll
-        for (int ct = 0; ct < CT; ++ct) b[ct] = *(const v4i*)(st + (FA + 2 * (CT * wc + ct) + ks) * 1024);
+        for (int p = 0; p < 4; ++p) {
+          a[ks][p] = *(const v4i*)(st + (2 * (p * WR + wr) + ks) * 1024);
+          if (p < CT) b[ks][p] = *(const v4i*)(st + (FA + 2 * (CT * wc + p) + ks) * 1024);
+        }
+      }
+      issue(std::integral_constant<int, (decltype(u)::value + DL - 1) % DL>{}, min(kt + DL - 1, KT - 1));
 #pragma unroll
-        for (int p = 0; p < 4; ++p) a[p] = *(const v4i*)(st + (2 * (p * WR + wr) + ks) * 1024);
+      for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
         for (int p = 0; p < 4; ++p)
 #pragma unroll
-          for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[p], b[ct], acc[ct][p]);
+          for (int ct = 0; ct < CT; ++ct) acc[ct][p] = mfma32_i8(a[ks][p], b[ks][ct], acc[ct][p]);
+      // schedule: all LDS reads, then MFMAs with the direct loads between them
+      __builtin_amdgcn_sched_group_barrier(0x100, 8 + 2 * CT, 0);
+#pragma unroll
+      for (int q = 0; q < LPW; ++q) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
       }
+      __builtin_amdgcn_sched_group_barrier(0x008, 8 * CT - LPW, 0);
     };
     using U0 = std::integral_constant<int, 0>;
     using U1 = std::integral_constant<int, 1>;
@@ -514,6 +528,7 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
       return rotate_cfg<2, 2, 4, 4>(p, m_blk);
     case 9:
       return rotate_cfg<2, 2, 2, 4>(p, m_blk);
+
     default:
       return rotate_cfg<2, 2, 2, 3>(p, m_blk);
   }
