@@ -175,10 +175,11 @@ KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): 
            ("rotate", "fp64"): ("k_rot64", "k_fp64.hip"), ("grid", "fp64"): ("k_grid64", "k_fp64.hip")}
 
 
-def committed_traffic(stage, precision, workload):
+def committed_traffic(stage, precision, workload, tuning):
     """HBM bytes per launch of the stage's kernel from the committed rocprofv3
     summaries (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when
-    none matches the current kernel source."""
+    none matches the current kernel source, or when the summary was taken with
+    the built-in launch parameters and this run's tuner chose others."""
     import glob
     import hashlib
     key = KERNELS.get((stage, precision))
@@ -192,6 +193,8 @@ def committed_traffic(stage, precision, workload):
                 continue
             kv = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
             if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("sha256_16") == sha:
+                if kv.get("tuning") == "builtin" and tuning and any(tuning.values()):
+                    return None
                 return float(kv["traffic_bytes_per_launch"])
     return None
 
@@ -299,7 +302,7 @@ def main():
     if flops is not None:
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": committed_traffic(dom, args.precision, args.workload), "kernel": KERNELS.get(
+                "traffic": committed_traffic(dom, args.precision, args.workload, tuning), "kernel": KERNELS.get(
                     (dom, args.precision), (dom,))[0], "avg_launch_ms": avg_ms, "launches_per_step": prof[dom][1],
                 "peak_source": peak_name}
         if args.precision == "mixed" and dom == "rotate":
