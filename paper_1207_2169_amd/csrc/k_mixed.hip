@@ -99,7 +99,10 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   // slots, each its own LDS array so that the compiler can tell them apart
   static_assert(DL == 0 || DL == 3 || DL == 4, "ring depth");
   constexpr int FA = 8 * WR, FB = 2 * CT * WC, FS = FA + FB;
-  constexpr int SMEM = DL ? FS * 1024 : 2 * (A_STAGE + B_STAGE);
+  // slot 0 also holds the epilogue's per-wave-row partials (EPI 1), which can
+  // be larger than a slice
+  constexpr int PS_BYTES = EPI == 1 ? WR * BN * NP * 8 : 0;
+  constexpr int SMEM = DL ? (FS * 1024 > PS_BYTES ? FS * 1024 : PS_BYTES) : 2 * (A_STAGE + B_STAGE);
   __shared__ __attribute__((aligned(1024))) int8_t smem[SMEM];
   __shared__ __attribute__((aligned(1024))) int8_t smem1[DL ? FS * 1024 : 16];
   __shared__ __attribute__((aligned(1024))) int8_t smem2[DL ? FS * 1024 : 16];
@@ -324,7 +327,22 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
 
   // per-wave-row partial sums (EPI 1) reuse the staging buffers, free after the last barrier
   double* Ps = (double*)smem;  // [WR][BN][NP]
-  static_assert(WR * BN * NP * 8 <= 2 * (A_STAGE + B_STAGE), "LDS reuse");
+  static_assert(PS_BYTES <= SMEM, "LDS reuse");
+  // With two column tiles, the second tile's plane sums wait in the free ring
+  // slots 1 and 2 while the first tile is finished (direct-load rotation,
+  // single trait): 32 registers fewer across the epilogue, which otherwise
+  // spills.  Each thread reads back only its own values.
+  constexpr bool STASH = DL && EPI == 1 && CT == 2;
+  static_assert(!STASH || 16 * NT * 4 <= FS * 1024, "stash size");
+  if constexpr (STASH) {
+    int* sh = (int*)smem1;
+    int* sl = (int*)smem2;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      sh[e * NT + tid] = hi[1][e];
+      sl[e * NT + tid] = lo[1][e];
+    }
+  }
   const int64_t ss = snp_stride(PL);
 
   // one column tile at a time (the scheduler is kept from overlapping the
@@ -334,6 +352,17 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     __builtin_amdgcn_sched_barrier(0);
     const int cl = 32 * (CT * wc + ct) + (lane & 31);
     const int64_t col = n0 + cl;
+    int hc[16], lc[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      if (STASH && ct == 1) {
+        hc[e] = ((const int*)smem1)[e * NT + tid];
+        lc[e] = ((const int*)smem2)[e * NT + tid];
+      } else {
+        hc[e] = hi[ct][e];
+        lc[e] = lo[ct][e];
+      }
+    }
     double v[PL];
 #pragma unroll
     for (int a = 0; a < PL; ++a) v[a] = vS[cl * PL + a];
@@ -348,7 +377,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int rr = rb0 + r, e = 4 * gq + r;
-        double x = fma((double)hi[ct][e], 65536.0, (double)lo[ct][e]) * zS[rr];
+        double x = fma((double)hc[e], 65536.0, (double)lc[e]) * zS[rr];
 #pragma unroll
         for (int a = 0; a < PL; ++a) x -= Qs[rr * PL + a] * v[a];
         xs[r] = x;
@@ -471,6 +500,18 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
   for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + off) = pk[q];
 }
 
+// Ring depth actually used: a four-slot ring whose LDS (slots, the larger
+// slot 0 for the single-trait partials, epilogue tables) would not fit a CU
+// falls back to three slots.
+template <int PL, int EPI, int CT, int WR, int WC, int DL>
+constexpr int rot_ring() {
+  constexpr int BM = 32 * WR, BN = 32 * CT * WC, NP = PL + 2, FS = 8 * WR + 2 * CT * WC;
+  constexpr int ps = EPI == 1 ? WR * BN * NP * 8 : 0;
+  constexpr int tab = (BM * PL + BM + BN * PL + (EPI == 1 ? BM * NP : 0)) * 8;
+  constexpr int lds = (FS * 1024 > ps ? FS * 1024 : ps) + (DL - 1) * FS * 1024 + tab;
+  return (DL == 4 && lds > 159 * 1024) ? 3 : DL;
+}
+
 template <int CT, int WR, int WC, int DL>
 static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   constexpr int BN = 32 * CT * WC;
@@ -484,8 +525,8 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   dim3 block(64 * WR * WC);
 #define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                         \
   case PLV:                                                                                                        \
-    k_rot_i8<PLV, EPI, CT, WR, WC, DL><<<grid, block, 0, p.stream>>>(p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd,  \
-                                                                 W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);       \
+    k_rot_i8<PLV, EPI, CT, WR, WC, rot_ring<PLV, EPI, CT, WR, WC, DL>()><<<grid, block, 0, p.stream>>>(          \
+        p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);                  \
     break;
   if (p.fused_t1) {
     switch (p.pL) {

@@ -28,16 +28,17 @@ def _outputs(w):
 
 
 # n_pad = 256, 384, 512: 4, 6 and 8 K slices of 64 (every remainder of the
-# three-slot ring of the direct-load rotations); CLAK-Chol rotates triangular
-# tiles of 1 to n_pad / 64 slices
-@pytest.mark.parametrize("t,n,chol", [(1, 300, False), (150, 300, False), (1, 200, False), (1, 450, False),
-                                      (1, 450, True)])
-def test_every_tuning_is_bitwise_identical(t, n, chol):
+# three- and four-slot rings of the direct-load rotations); CLAK-Chol rotates
+# triangular tiles of 1 to n_pad / 64 slices; p_L = 8 (workload 4) gives the
+# single-trait epilogue its largest per-wave-row partials
+@pytest.mark.parametrize("t,n,chol,config", [(1, 300, False, 2), (150, 300, False, 2), (1, 200, False, 2),
+                                             (1, 450, False, 2), (1, 450, True, 2), (1, 450, False, 4)])
+def test_every_tuning_is_bitwise_identical(t, n, chol, config):
     import torch
 
     from paper_1207_2169_amd import clak
-    w = make_workload(2, n=n, m=700, t=t, kin_cols=2 * n)
-    print(f"tuning sweep t={t} n={n} chol={chol}", flush=True)
+    w = make_workload(config, n=n, m=700, t=t, kin_cols=2 * n)
+    print(f"tuning sweep t={t} n={n} chol={chol} p_L={w.pL}", flush=True)
     G = torch.from_numpy(w.genotypes(0, w.m)).cuda()
     with _plan(w, w.m, clak.CLAK_CHOL if chol else 0) as plan:
         ref = _outputs(w)
