@@ -203,8 +203,8 @@ def stage_flops(stage, w, block):
     """Algorithmic flops of one launch of a stage on a full block."""
     if stage == "rotate":
         f = 2.0 * w.n * w.n * block
-        if w.t == 1:  # the fused reduction of the single-trait kernel
-            f += 2.0 * w.n * block * (w.pL + 2)
+        if w.t == 1:  # single trait: the linear sums (extra row tile) and d^T (x o x)
+            f += 2.0 * w.n * block * (w.pL + 1) + 3.0 * w.n * block
         return f
     if stage == "grid":
         return 2.0 * w.n * block * w.t * (w.pL + 2)

@@ -128,7 +128,7 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   const size_t np = p.n_pad, pl = p.pL, tp = p.t_pad, mb = p.mb_pad;
   Workspace tmp;
   Workspace& W = w ? *w : tmp;
-  W.Zt = (double*)take(8 * np * np);
+  W.Zt = (double*)take(8 * p.zrows * np);
   W.w = (double*)take(8 * np);
   W.evE = (double*)take(8 * np);
   W.dstat = (int*)take(sizeof(int) * DS_COUNT);
@@ -148,9 +148,10 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
     W.D64 = (double*)take(8 * tp * np);
   }
   if (p.prec == CLAK_PREC_MIXED) {
-    W.Zd = (int8_t*)take(4 * np * np);
-    W.zs = (double*)take(8 * np);
+    W.Zd = (int8_t*)take(4 * p.zrows * np);
+    W.zs = (double*)take(8 * p.zrows);
   }
+  if (lin_rows(p)) W.Cq = (double*)take(8 * pl * (pl + 1));
   if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) {
     W.Vd = (int8_t*)take(4 * tp * (pl + 1) * np);
     W.Dd = (int8_t*)take(4 * tp * np);
@@ -218,6 +219,8 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
   p->mb_pad = roundup(max_block, SNP_PAD);
   p->t_pad = roundup(t, TRAIT_PAD);
   p->fused_t1 = (t == 1);
+  p->zlin = (lin_rows(*p) && n + p_L + 1 <= p->n_pad) ? n : p->n_pad;
+  p->zrows = p->n_pad + ((lin_rows(*p) && p->zlin == p->n_pad) ? ZEXT : 0);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(CLAK_E_DEVICE, "plan_create: no HIP device");
@@ -298,7 +301,7 @@ static clak_status chol_factor(Plan* p, const double* d_h2) {
   if (rs != rocblas_status_success) return fail(CLAK_E_DEVICE, "set_traits: rocsolver_dtrtri status %d", (int)rs);
   HIP_TRY(launch_chol_fix(*p));
   HIP_TRY(launch_check_eigen(*p));
-  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p));
+  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p, 0, p->n_pad));
   HIP_TRY(launch_rotate_real(*p, W.XL, np, p->pL, W.XLt, np));
   HIP_TRY(launch_rotate_real(*p, W.QL, np, p->pL, W.Qt, np));
   s = sync_and_read_status(p);
@@ -311,7 +314,7 @@ static clak_status chol_factor(Plan* p, const double* d_h2) {
 static clak_status finish_eigen(Plan* p) {
   // zero the status words, validate the eigenpairs, split Z^T into digits
   HIP_TRY(launch_check_eigen(*p));
-  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p));
+  if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p, 0, p->n_pad));
   clak_status s = sync_and_read_status(p);
   if (s != CLAK_OK) return s;
   if (p->hstat[DS_EIGVAL]) return fail(CLAK_E_ARG, "non-finite eigenvalues or eigenvectors");
@@ -432,6 +435,11 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   HIP_TRY(hipMemcpy2DAsync(W.tpar + p->pL * p->pL + p->pL + 1, sizeof(double) * ts, d_h2, sizeof(double),
                            sizeof(double), p->t, hipMemcpyDeviceToDevice, p->stream));
   HIP_TRY(launch_traits(*p));
+  if (lin_rows(*p)) {
+    // the extra rotation rows U^T = (Z W)^T and their digits
+    HIP_TRY(launch_uproj(*p));
+    HIP_TRY(launch_split_digits(*p, p->zlin, p->zrows));
+  }
   s = sync_and_read_status(p);
   if (s) return s;
   if (p->hstat[DS_TRAIT_ARG])

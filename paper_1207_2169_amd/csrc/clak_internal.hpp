@@ -36,7 +36,9 @@ __host__ __device__ inline int64_t roundup(int64_t x, int64_t m) { return (x + m
 //   2pL + 1      cell flag of the SNP (0 ok, 1 degenerate, 2 bad genotype)
 //   2pL + 2      max_k |x~_k| of the rotated, centred SNP (mixed path; written
 //                by an atomic max on its bit pattern, so it is order-independent)
-__host__ __device__ inline int64_t snp_stride(int64_t pL) { return 2 * pL + 3; }
+//   [2pL+3, 3pL+4)  single-trait mixed path: the linear cell sums c' and r'
+//                (written by the rotation's U^T rows, see zlin)
+__host__ __device__ inline int64_t snp_stride(int64_t pL) { return 3 * pL + 4; }
 // Per-trait parameters written by the trait kernel (doubles, stride trait_stride):
 //   [0, pL*pL)   L^{-1} (row-major, lower), L L^T = S_TL
 //   [pL*pL, pL*pL+pL)  u = S_TL^{-1} b_T
@@ -86,7 +88,8 @@ inline int64_t genotype_row_units(int g_dtype, int64_t n) { return g_dtype == CL
 struct Workspace {
   Slot slot[NSLOTS];
   // common
-  double* Zt = nullptr;     // n_pad x n_pad: row k (stride n_pad) = eigenvector k, zero padded
+  double* Zt = nullptr;     // zrows x n_pad: row k (stride n_pad) = eigenvector k, zero padded; rows zlin +
+                            // q <= pL of a single-trait mixed plan hold column q of U = Z W
   double* w = nullptr;      // n_pad eigenvalues (zero beyond n)
   double* evE = nullptr;    // n_pad, eigensolver scratch
   int* dstat = nullptr;     // DS_COUNT device status words
@@ -99,6 +102,7 @@ struct Workspace {
   double* Phi = nullptr;    // CLAK_CHOL: n_pad x n_pad copy of Phi (lower triangle used)
   double* XL = nullptr;     // CLAK_CHOL: n_pad x pL copy of X_L (rotated at set_traits)
   double* tpar = nullptr;   // t_pad x trait_stride
+  double* Cq = nullptr;     // single-trait mixed: pL x (pL+1) row-major, C = Q_L^T U (centring of the extra rows)
   // per block (the slot selected for the block being launched)
   int8_t* Gp = nullptr;     // mb_pad SNP rows x n_pad individuals, K-tiled (kt32), zero padded
   double* sstat = nullptr;  // mb_pad x snp_stride
@@ -110,8 +114,8 @@ struct Workspace {
   double* D64 = nullptr;    // t_pad x n_pad: d_j
   double* part = nullptr;   // fused t = 1 kernel: [n_pad/64][pL+2][mb_pad] partial sums
   // mixed path
-  int8_t* Zd = nullptr;     // 4 planes x n_pad rows (Z^T) x n_pad, K-tiled (kt32)
-  double* zs = nullptr;     // n_pad: per-row digit scale (value = zs * sum digits 256^(3-p))
+  int8_t* Zd = nullptr;     // 4 planes x zrows rows (Z^T) x n_pad, K-tiled (kt32)
+  double* zs = nullptr;     // zrows: per-row digit scale (value = zs * sum digits 256^(3-p))
   int8_t* Xd = nullptr;     // 8 planes x mb_pad rows (SNPs) x n_pad, K-tiled (kt32): digits of x, then x^2
   int8_t* Vd = nullptr;     // 4 planes x t_pad*(pL+1) rows (vrow order) x n_pad, K-tiled (kt32)
   int8_t* Dd = nullptr;     // 4 planes x t_pad rows x n_pad, K-tiled (kt32)
@@ -126,6 +130,14 @@ struct Plan {
   int prec = CLAK_PREC_FP64;
   uint32_t flags = 0;
   int64_t n_pad = 0, mb_pad = 0, t_pad = 0;
+  // Rows of the rotation operand.  A single-trait mixed plan appends the pL + 1
+  // rows of U^T = (Z W)^T (W: the trait operand columns) at row zlin, so that
+  // the rotation also yields the linear cell sums c' = W_c^T x~ and
+  // r' = W_r^T x~ of each SNP (U^T (g - Q_L v) = W^T x~): in the zero padding
+  // rows n .. when n + pL + 1 <= n_pad (zrows = n_pad), else in one more tile
+  // of ZEXT rows (zlin = n_pad, zrows = n_pad + ZEXT).  Other plans: zlin =
+  // zrows = n_pad.
+  int64_t zrows = 0, zlin = 0;
   int device = 0;
   hipStream_t stream = nullptr;
   void* rocblas = nullptr;  // rocblas_handle
@@ -162,6 +174,11 @@ inline int ingest_splits(const Plan& p) {
   return (int)(windows < ING_MAX_SPLITS ? windows : ING_MAX_SPLITS);
 }
 
+constexpr int64_t ZEXT = 64;  // rows of the extra rotation tile (one 64-row tile)
+// Single-trait mixed plans form the linear cell sums in the rotation's U^T
+// rows; its other rows give only the quadratic sum a.
+inline bool lin_rows(const Plan& p) { return p.fused_t1 && p.prec == CLAK_PREC_MIXED; }
+
 // Points the per-block buffers of the workspace at slot k.
 inline void select_slot(Plan& p, int k) {
   const Slot& s = p.ws.slot[k];
@@ -189,11 +206,12 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
 
 // ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
 // set-up
-hipError_t launch_split_digits(const Plan& p);
+hipError_t launch_split_digits(const Plan& p, int64_t r0, int64_t r1);
 hipError_t launch_covariates(const Plan& p, const double* d_XL, int64_t ld);
 hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64_t ncols, double* out,
                               int64_t ldo);
 hipError_t launch_traits(const Plan& p);
+hipError_t launch_uproj(const Plan& p);
 hipError_t launch_vc(const Plan& p, int method, double* h2, double* s2, double* ll);
 hipError_t launch_check_eigen(const Plan& p);
 hipError_t launch_chol_check(const Plan& p);

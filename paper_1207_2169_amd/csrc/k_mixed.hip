@@ -44,9 +44,12 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 // term (Z^T Q_L)[k] . v(i) is subtracted (FP64).  Then
 //   EPI 0: the value is stored (SNP-major) and the SNP's max |x~_k| is raised
 //          by an atomic max, for the digit encoding of the grid operand;
-//   EPI 1: (single trait) the cell sums c', r', a of this tile's rows are
-//          formed in FP64 against the FP64 trait operand and written as one
-//          partial per (row tile, SNP); x~ never leaves the chip.
+//   EPI 1: (single trait) the quadratic cell sum a = d^T (x~ o x~) of this
+//          tile's rows is formed in FP64 and written as one partial per (row
+//          tile, SNP); x~ never leaves the chip.  Rows zl .. zl + p_L of the
+//          operand (zero padding rows, or one more tile) hold U^T = (Z W)^T,
+//          centred by C = Q_L^T U: for them x~ is a linear cell sum (c', then
+//          r') of the SNP, which goes to the SNP's statistics.
 //
 // v_mfma_i32_32x32x32_i8 lane layout (gfx950): lane l supplies 16 bytes of row
 // l%32 of A and of column l%32 of B, the same 16 values of the 32-deep
@@ -85,11 +88,11 @@ __device__ __forceinline__ void lds_barrier() {
 
 template <int PL, int EPI, int CT, int WR, int WC, int DL>
 __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
-    k_rot_i8(int64_t np, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri, const int8_t* __restrict__ Zd,
-             const double* __restrict__ zs, const int8_t* __restrict__ Gp, const double* __restrict__ Qt,
-             double* __restrict__ sstat, double* __restrict__ X, const double* __restrict__ V,
-             const double* __restrict__ Dv, double* __restrict__ part) {
-  constexpr int NT = 64 * WR * WC, BM = 32 * WR, BN = 32 * CT * WC, BK = 64, NP = PL + 2;
+    k_rot_i8(int64_t np, int64_t nz, int64_t zl, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri,
+             const int8_t* __restrict__ Zd, const double* __restrict__ zs, const int8_t* __restrict__ Gp,
+             const double* __restrict__ Qt, const double* __restrict__ Cq, double* __restrict__ sstat,
+             double* __restrict__ X, const double* __restrict__ Dv, double* __restrict__ part) {
+  constexpr int NT = 64 * WR * WC, BM = 32 * WR, BN = 32 * CT * WC, BK = 64;
   constexpr int A_STAGE = 4 * BM * LROW, B_STAGE = BN * LROW;
   constexpr int A_LD = 16 * BM / NT, B_LD = 4 * BN / NT;  // 16-byte loads per thread per slice
   static_assert(16 * BM % NT == 0 && 4 * BN % NT == 0, "tile / thread mismatch");
@@ -101,22 +104,22 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   constexpr int FA = 8 * WR, FB = 2 * CT * WC, FS = FA + FB;
   // slot 0 also holds the epilogue's per-wave-row partials (EPI 1), which can
   // be larger than a slice
-  constexpr int PS_BYTES = EPI == 1 ? WR * BN * NP * 8 : 0;
+  constexpr int PS_BYTES = EPI == 1 ? WR * BN * 8 : 0;
   constexpr int SMEM = DL ? (FS * 1024 > PS_BYTES ? FS * 1024 : PS_BYTES) : 2 * (A_STAGE + B_STAGE);
   __shared__ __attribute__((aligned(1024))) int8_t smem[SMEM];
   __shared__ __attribute__((aligned(1024))) int8_t smem1[DL ? FS * 1024 : 16];
   __shared__ __attribute__((aligned(1024))) int8_t smem2[DL ? FS * 1024 : 16];
   __shared__ __attribute__((aligned(1024))) int8_t smem3[DL == 4 ? FS * 1024 : 16];
   // epilogue tables, fetched while the first stage loads
-  constexpr int NTAB = BM * PL + BM + BN * PL + (EPI == 1 ? BM * NP : 0);
+  constexpr int NTAB = BM * PL + BM + BN * PL + (EPI == 1 ? BM : 0);
   __shared__ double tab[NTAB];
   double* Qs = tab;             // [BM][PL]   (Z^T Q_L) rows of the tile
   double* zS = Qs + BM * PL;    // [BM]       digit scales of Z^T rows
   double* vS = zS + BM;         // [BN][PL]   centring coefficients of the SNPs
-  double* Vs = vS + BN * PL;    // [BM][NP]   trait operand rows (EPI 1)
+  double* Vs = vS + BN * PL;    // [BM]       d of the tile's rows (EPI 1)
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wr = wid / WC, wc = wid % WC;
-  const int64_t ntm = np / BM;
+  const int64_t ntm = nz / BM;
   const int64_t sg = 8 / rg, gm = (ntm + rg - 1) / rg, gn = (ntn + sg - 1) / sg;
   const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
   // lower-triangular Z^T (CLAK-Chol): row tile tm needs the first tm + 1 K
@@ -126,7 +129,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   const int64_t tn = (xcd / rg) * gn + idx / gm;
   if (tm < 0 || tm >= ntm || tn >= ntn || idx >= gm * gn) return;
   const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t zplane = np * np;
+  const int64_t zplane = nz * np;
   const int KT = (int)((tri ? min(np, m0 + BM) : np) / BK);
 
   v16i acc[CT][4];
@@ -141,14 +144,15 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   // reads, so the LDS stores are free of bank conflicts.
   auto load_tables = [&]() {
     const int64_t ss = snp_stride(PL);
-    for (int e = tid; e < BM * PL; e += NT) Qs[e] = Qt[m0 + e / PL + (e % PL) * np];
+    for (int e = tid; e < BM * PL; e += NT) {
+      const int64_t row = m0 + e / PL;
+      const int a = e % PL;
+      Qs[e] = (row >= zl && row <= zl + PL) ? Cq[a * (PL + 1) + (row - zl)] : (row < np ? Qt[row + a * np] : 0.0);
+    }
     for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
     for (int e = tid; e < BN * PL; e += NT) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
     if (EPI == 1)
-      for (int e = tid; e < BM * NP; e += NT) {
-        const int r = e / NP, q = e % NP;
-        Vs[e] = (q <= PL) ? V[q * np + m0 + r] : Dv[m0 + r];
-      }
+      for (int e = tid; e < BM; e += NT) Vs[e] = m0 + e < np ? Dv[m0 + e] : 0.0;
   };
 
   if constexpr (DL) {
@@ -179,7 +183,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
         const int8_t* src;
         if (q < LPA) {
           const int h = fi & 1, r = (fi >> 1) % WR, pl = (fi >> 1) / WR;
-          src = za + pl * zplane + ((s0 + h) * np + 32 * r) * 32;
+          src = za + pl * zplane + ((s0 + h) * nz + 32 * r) * 32;
         } else {
           const int h = (fi - FA) & 1, c = (fi - FA) >> 1;
           src = gb + ((s0 + h) * mbp + 32 * c) * 32;
@@ -256,7 +260,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
       for (int q = 0; q < A_LD; ++q) {  // group (tid + NT q) / 64: half g % 2, row block (g / 2) % (BM / 32), plane
         const int g = (tid + NT * q) >> 6;
         const int kh = g & 1, rb32 = (g >> 1) % (BM / 32), pl = (g >> 1) / (BM / 32);
-        ra[q] = *(const v4i*)(Zd + pl * zplane + kt32(m0 + 32 * rb32 + srow, k0 + 32 * kh, np) + 16 * sch);
+        ra[q] = *(const v4i*)(Zd + pl * zplane + kt32(m0 + 32 * rb32 + srow, k0 + 32 * kh, nz) + 16 * sch);
       }
   #pragma unroll
       for (int q = 0; q < B_LD; ++q) {
@@ -326,7 +330,8 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     }
 
   // per-wave-row partial sums (EPI 1) reuse the staging buffers, free after the last barrier
-  double* Ps = (double*)smem;  // [WR][BN][NP]
+  double* Ps = (double*)smem;  // [WR][BN]
+  const bool ext = m0 >= np;   // the extra row tile holding U^T (EPI 1): no partial
   static_assert(PS_BYTES <= SMEM, "LDS reuse");
   // With two column tiles, the second tile's plane sums wait in the free ring
   // slots 1 and 2 while the first tile is finished (direct-load rotation,
@@ -366,10 +371,8 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     double v[PL];
 #pragma unroll
     for (int a = 0; a < PL; ++a) v[a] = vS[cl * PL + a];
-    double ps[NP];
+    double pa = 0.0;
     double mx = 0.0;
-#pragma unroll
-    for (int q = 0; q < NP; ++q) ps[q] = 0.0;
 #pragma unroll
     for (int gq = 0; gq < 4; ++gq) {
       const int rb0 = 32 * wr + 8 * gq + 4 * (lane >> 5);  // row within the tile
@@ -384,10 +387,11 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
         if (EPI == 0) {
           mx = fmax(mx, fabs(x));
         } else {
-#pragma unroll
-          for (int q = 0; q <= PL; ++q) ps[q] += Vs[rr * NP + q] * x;
-          ps[PL + 1] += Vs[rr * NP + PL + 1] * x * x;
-          __builtin_amdgcn_sched_barrier(0);  // one row's table reads live at a time
+          const int64_t row = m0 + rr;
+          if (row >= zl && row <= zl + PL)
+            sstat[col * ss + 2 * PL + 3 + (row - zl)] = x;
+          else
+            pa += Vs[rr] * x * x;
         }
       }
       if (EPI == 0) *(v4d*)(X + col * np + m0 + rb0) = (v4d){xs[0], xs[1], xs[2], xs[3]};
@@ -398,23 +402,19 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
       if ((lane >> 5) == 0 && col < mb)
         atomicMax((unsigned long long*)(sstat + col * ss + 2 * PL + 2), (unsigned long long)__double_as_longlong(m));
     } else {
-#pragma unroll
-      for (int q = 0; q < NP; ++q) {
-        const double sq = ps[q] + __shfl_xor(ps[q], 32, 64);
-        if ((lane >> 5) == 0) Ps[(wr * BN + cl) * NP + q] = sq;
-      }
+      const double sq = pa + __shfl_xor(pa, 32, 64);
+      if ((lane >> 5) == 0) Ps[wr * BN + cl] = sq;
     }
   }
-  if (EPI == 1) {
+  if (EPI == 1 && !ext) {
     __syncthreads();
     // the WR row slices of the tile combine (fixed order); one partial per
     // (row tile, SNP)
-    for (int e = tid; e < BN * NP; e += NT) {
-      const int cl = e % BN, q = e / BN;
+    for (int cl = tid; cl < BN; cl += NT) {
       double sum = 0.0;
 #pragma unroll
-      for (int w = 0; w < WR; ++w) sum += Ps[(w * BN + cl) * NP + q];
-      part[(tm * NP + q) * mbp + n0 + cl] = sum;
+      for (int w = 0; w < WR; ++w) sum += Ps[w * BN + cl];
+      part[tm * mbp + n0 + cl] = sum;
     }
   }
 }
@@ -440,16 +440,19 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
 //   9: 2, 2, 2, DL4 as 0, three slices in flight (one work-group per CU)
 constexpr int ROT_BM = 64;
 static_assert(ROT_CONFIGS == 10, "rotation configurations");
-static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0, "rotation tiles must divide the paddings");
+static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0 && ZEXT == ROT_BM, "rotation tiles must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
 // order and solves the cell (Schur complement, FP64).  A work-group takes 64
 // SNPs; its four waves sum interleaved row tiles, then wave 0 adds the four.
-template <int PL>
+// LIN 0 (FP64 path): each partial holds c', r' and a.  LIN 1 (mixed path):
+// each partial holds a; c' and r' are in the SNP's statistics (written by the
+// rotation's extra row tile).
+template <int PL, int LIN>
 __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp,
                                                 const double* __restrict__ part, const double* __restrict__ tpar,
                                                 const double* __restrict__ sstat, uint32_t flags, CellOut out) {
-  constexpr int NP = PL + 2;
+  constexpr int NP = LIN ? 1 : PL + 2;  // partial values per row tile
   __shared__ double red[4][64][NP + 1];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + lane;
@@ -467,7 +470,15 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
   if (wid != 0 || i >= m_blk) return;
 #pragma unroll
   for (int q = 0; q < NP; ++q) s[q] = ((red[0][lane][q] + red[1][lane][q]) + red[2][lane][q]) + red[3][lane][q];
-  schur_store<PL>(s, s[PL], s[PL + 1], tpar, sstat + i * snp_stride(PL), flags, i, 0, out);
+  const double* st = sstat + i * snp_stride(PL);
+  if constexpr (LIN) {
+    double c[PL];
+#pragma unroll
+    for (int a = 0; a < PL; ++a) c[a] = st[2 * PL + 3 + a];
+    schur_store<PL>(c, st[3 * PL + 3], s[0], tpar, st, flags, i, 0, out);
+  } else {
+    schur_store<PL>(s, s[PL], s[PL + 1], tpar, st, flags, i, 0, out);
+  }
 }
 
 // Digit encoding of the rotated SNPs for the grid contraction: x with scale
@@ -505,9 +516,9 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
 // falls back to three slots.
 template <int PL, int EPI, int CT, int WR, int WC, int DL>
 constexpr int rot_ring() {
-  constexpr int BM = 32 * WR, BN = 32 * CT * WC, NP = PL + 2, FS = 8 * WR + 2 * CT * WC;
-  constexpr int ps = EPI == 1 ? WR * BN * NP * 8 : 0;
-  constexpr int tab = (BM * PL + BM + BN * PL + (EPI == 1 ? BM * NP : 0)) * 8;
+  constexpr int BM = 32 * WR, BN = 32 * CT * WC, FS = 8 * WR + 2 * CT * WC;
+  constexpr int ps = EPI == 1 ? WR * BN * 8 : 0;
+  constexpr int tab = (BM * PL + BM + BN * PL + (EPI == 1 ? BM : 0)) * 8;
   constexpr int lds = (FS * 1024 > ps ? FS * 1024 : ps) + (DL - 1) * FS * 1024 + tab;
   return (DL == 4 && lds > 159 * 1024) ? 3 : DL;
 }
@@ -517,20 +528,20 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   constexpr int BN = 32 * CT * WC;
   static_assert(32 * WR == ROT_BM && SNP_PAD % BN == 0, "rotation tile");
   const Workspace& W = p.ws;
-  const int64_t ntn = roundup(m_blk, SNP_PAD) / BN, ntm = p.n_pad / ROT_BM;
+  const int64_t ntn = roundup(m_blk, SNP_PAD) / BN, ntm = p.zrows / ROT_BM;
   const int rg = p.rot_rg ? p.rot_rg : ROT_RG_DEFAULT;
   const int tri = (p.flags & CLAK_CHOL) ? 1 : 0;
   const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
   dim3 grid((unsigned)(8 * gm * gn));
   dim3 block(64 * WR * WC);
-#define CLAK_ROT(PLV, EPI, XP, VP, DP, PP)                                                                         \
+#define CLAK_ROT(PLV, EPI, XP, DP, PP)                                                                         \
   case PLV:                                                                                                        \
     k_rot_i8<PLV, EPI, CT, WR, WC, rot_ring<PLV, EPI, CT, WR, WC, DL>()><<<grid, block, 0, p.stream>>>(          \
-        p.n_pad, m_blk, p.mb_pad, ntn, rg, tri, W.Zd, W.zs, W.Gp, W.Qt, W.sstat, XP, VP, DP, PP);                  \
+        p.n_pad, p.zrows, p.zlin, m_blk, p.mb_pad, ntn, rg, tri, W.Zd, W.zs, W.Gp, W.Qt, W.Cq, W.sstat, XP, DP, PP); \
     break;
   if (p.fused_t1) {
     switch (p.pL) {
-#define CLAK_R1(PLV) CLAK_ROT(PLV, 1, nullptr, W.V64, W.D64, W.part)
+#define CLAK_R1(PLV) CLAK_ROT(PLV, 1, nullptr, W.D64, W.part)
       CLAK_R1(1) CLAK_R1(2) CLAK_R1(3) CLAK_R1(4) CLAK_R1(5) CLAK_R1(6) CLAK_R1(7) CLAK_R1(8)
 #undef CLAK_R1
       default:
@@ -539,7 +550,7 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
     return hipGetLastError();
   }
   switch (p.pL) {
-#define CLAK_R0(PLV) CLAK_ROT(PLV, 0, W.X64, nullptr, nullptr, nullptr)
+#define CLAK_R0(PLV) CLAK_ROT(PLV, 0, W.X64, nullptr, nullptr)
     CLAK_R0(1) CLAK_R0(2) CLAK_R0(3) CLAK_R0(4) CLAK_R0(5) CLAK_R0(6) CLAK_R0(7) CLAK_R0(8)
 #undef CLAK_R0
     default:
@@ -904,9 +915,12 @@ hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out) {
   const Workspace& W = p.ws;
   dim3 fgrid((unsigned)((m_blk + 63) / 64));
   const int64_t nrt = p.prec == CLAK_PREC_MIXED ? p.n_pad / ROT_BM : p.n_pad / 64;
-#define CLAK_F1(PLV)                                                                                          \
-  case PLV:                                                                                                   \
-    k_fin_t1<PLV><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
+#define CLAK_F1(PLV)                                                                                            \
+  case PLV:                                                                                                     \
+    if (lin_rows(p))                                                                                            \
+      k_fin_t1<PLV, 1><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
+    else                                                                                                        \
+      k_fin_t1<PLV, 0><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
     break;
   switch (p.pL) {
     CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)

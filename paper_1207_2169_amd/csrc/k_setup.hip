@@ -27,28 +27,34 @@ hipError_t launch_check_eigen(const Plan& p) {
 // Row k of Z^T (eigenvector k) is stored as four int8 planes with one scale
 // per row: Z^T[k][i] ~= zs[k] * sum_p Zd[p][k][i] * 256^(3-p), zs[k] =
 // max_i |Z^T[k][i]| / QMAX.  Rounding error <= 0.5 zs[k] per entry.
-__global__ void k_split_digits(int64_t n, int64_t np, const double* __restrict__ Zt, int8_t* __restrict__ Zd,
-                               double* __restrict__ zs) {
+// Rows r0 + blockIdx.x of a layout of zr rows.  Rows below n and from zl on
+// (the U^T rows of a single-trait mixed plan) carry data, the rows between are
+// zero padding, and every row is zero beyond n.
+__global__ void k_split_digits(int64_t n, int64_t np, int64_t zr, int64_t zl, int64_t r0,
+                               const double* __restrict__ Zt, int8_t* __restrict__ Zd, double* __restrict__ zs) {
   __shared__ double red[16];
-  const int64_t k = blockIdx.x;
+  const int64_t k = r0 + blockIdx.x;
+  const bool live = k < n || k >= zl;
   const double* row = Zt + k * np;
   double mx = 0.0;
-  if (k < n)
+  if (live)
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, fabs(row[i]));
   mx = block_max(mx, red);
   const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
-  const int64_t plane = np * np;
+  const int64_t plane = zr * np;
   for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
     int8_t d[4] = {0, 0, 0, 0};
-    if (k < n && i < n) digits4(quantize(row[i], inv), d);
+    if (live && i < n) digits4(quantize(row[i], inv), d);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Zd[q * plane + kt32(k, i, np)] = d[q];
+    for (int q = 0; q < 4; ++q) Zd[q * plane + kt32(k, i, zr)] = d[q];
   }
   if (threadIdx.x == 0) zs[k] = mx / QMAX;
 }
 
-hipError_t launch_split_digits(const Plan& p) {
-  k_split_digits<<<dim3((unsigned)p.n_pad), dim3(256), 0, p.stream>>>(p.n, p.n_pad, p.ws.Zt, p.ws.Zd, p.ws.zs);
+hipError_t launch_split_digits(const Plan& p, int64_t r0, int64_t r1) {
+  if (r1 <= r0) return hipSuccess;
+  k_split_digits<<<dim3((unsigned)(r1 - r0)), dim3(256), 0, p.stream>>>(p.n, p.n_pad, p.zrows, p.zlin, r0, p.ws.Zt,
+                                                                          p.ws.Zd, p.ws.zs);
   return hipGetLastError();
 }
 
@@ -375,6 +381,49 @@ __global__ void __launch_bounds__(256) k_traits(int64_t n, int64_t np, int pL, i
       D64[j * np + k] = v[ncol];
     }
   }
+}
+
+// Single trait, mixed path: the trait operand carried back to the genotype
+// side.  The rotation forms x~ = Z^T (g - Q_L v) (Z^T: the rows of Zt, the
+// eigenvectors, or U^-T under CLAK-Chol); the linear cell sums of section 3's
+// inner loop, W^T x~ for the p_L + 1 operand columns W of the trait (c' and r'),
+// equal U^T (g - Q_L v) with U = Z W.  The columns of U become rows zl + q of
+// Zt, so the rotation yields them too, centred by C = Q_L^T U.
+// k_uproj: one thread per individual i, U[i][q] summed over the n eigen rows
+// in order (W is zero beyond n); rows zl + q for q > p_L up to zr are zero.
+__global__ void __launch_bounds__(256) k_uproj(int64_t n, int64_t np, int64_t zl, int64_t zr, int ncol,
+                                               const double* __restrict__ V64, double* __restrict__ Zt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= np) return;
+  for (int64_t q = 0; q < zr - zl; ++q) {
+    double acc = 0.0;
+    if (q < ncol && i < n) {
+      const double* wq = V64 + q * np;
+      for (int64_t k = 0; k < n; ++k) acc += Zt[k * np + i] * wq[k];
+    }
+    Zt[(zl + q) * np + i] = acc;
+  }
+}
+
+// C[a][q] = sum_i Q_L[i][a] U[i][q], one thread per entry.
+__global__ void __launch_bounds__(256) k_cproj(int64_t np, int64_t zl, int pL, const double* __restrict__ QL,
+                                               const double* __restrict__ Zt, double* __restrict__ Cq) {
+  const int ncol = pL + 1;
+  for (int e = threadIdx.x; e < pL * ncol; e += blockDim.x) {
+    const int a = e / ncol, q = e % ncol;
+    const double* u = Zt + (zl + q) * np;
+    double acc = 0.0;
+    for (int64_t i = 0; i < np; ++i) acc += QL[i + a * np] * u[i];
+    Cq[e] = acc;
+  }
+}
+
+hipError_t launch_uproj(const Plan& p) {
+  const Workspace& W = p.ws;
+  k_uproj<<<dim3((unsigned)((p.n_pad + 255) / 256)), 256, 0, p.stream>>>(p.n, p.n_pad, p.zlin, p.zrows,
+                                                                         (int)p.pL + 1, W.V64, W.Zt);
+  k_cproj<<<1, 256, 0, p.stream>>>(p.n_pad, p.zlin, (int)p.pL, W.QL, W.Zt, W.Cq);
+  return hipGetLastError();
 }
 
 hipError_t launch_traits(const Plan& p) {

@@ -40,6 +40,20 @@ def test_individual_padding(prec, n):
     _check(w, prec, 300)
 
 
+# Single trait, mixed path: the p_L + 1 rows U^T of the rotation sit in the
+# zero padding rows n .. n + p_L when n + p_L + 1 <= n_pad, else in one more
+# row tile; both sides of that boundary for p_L = 3 (workload 1) and p_L = 8
+# (workload 4), by CLAK-Eig and by CLAK-Chol.
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("n,config,chol", [(124, 1, False), (125, 1, False), (128, 1, False), (129, 1, False),
+                                           (119, 4, False), (120, 4, False), (124, 1, True), (128, 1, True)])
+def test_individual_padding_single_trait(prec, n, config, chol):
+    from paper_1207_2169_amd import clak
+    w = make_workload(config, n=n, m=300, t=1, kin_cols=2 * n)
+    print(f"single-trait padding n={n} p_L={w.pL} chol={chol}", flush=True)
+    _check(w, prec, 300, flags=clak.CLAK_CHOL if chol else 0)
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("m,block", [(257, 255), (513, 256), (520, 257)])
 def test_block_padding_single_trait(prec, m, block):
