@@ -327,7 +327,7 @@ clak_status clak_bed_close(clak_bed_t bed);
 
 /* Stages of clak_run_block timed by the profiler. */
 #define CLAK_STAGE_INGEST 0  /* genotype block -> int8 panel, per-SNP centring statistics */
-#define CLAK_STAGE_ROTATE 1  /* X~ = Z^T G (plus the fused single-trait reduction)      */
+#define CLAK_STAGE_ROTATE 1  /* X~ = Z^T G (single trait: plus the fused cell sums)     */
 #define CLAK_STAGE_ENCODE 2  /* digit encoding of X~ for the grid (mixed, several traits) */
 #define CLAK_STAGE_GRID 3    /* grid contraction + Schur solve, or the single-trait finish */
 #define CLAK_STAGE_COUNT 4
