@@ -142,17 +142,49 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   // (plane, 32-row block, half of the 64-byte slice); lane l of a group takes
   // row l % 32, chunk l / 32 of that half, the lane pattern of the fragment
   // reads, so the LDS stores are free of bank conflicts.
+  // every table value of this thread is loaded first, then stored, so the
+  // loads are in flight together
   auto load_tables = [&]() {
     const int64_t ss = snp_stride(PL);
-    for (int e = tid; e < BM * PL; e += NT) {
+    constexpr int JQ = (BM * PL + NT - 1) / NT, JZ = (BM + NT - 1) / NT, JV = (BN * PL + NT - 1) / NT;
+    constexpr int JD = EPI == 1 ? (BM + NT - 1) / NT : 0;
+    double tq[JQ], tz[JZ], tv[JV], td[JD > 0 ? JD : 1];
+#pragma unroll
+    for (int j = 0; j < JQ; ++j) {
+      const int e = tid + j * NT;
       const int64_t row = m0 + e / PL;
       const int a = e % PL;
-      Qs[e] = (row >= zl && row <= zl + PL) ? Cq[a * (PL + 1) + (row - zl)] : (row < np ? Qt[row + a * np] : 0.0);
+      tq[j] = 0.0;
+      if (e < BM * PL)
+        tq[j] = (row >= zl && row <= zl + PL) ? Cq[a * (PL + 1) + (row - zl)] : (row < np ? Qt[row + a * np] : 0.0);
     }
-    for (int e = tid; e < BM; e += NT) zS[e] = zs[m0 + e];
-    for (int e = tid; e < BN * PL; e += NT) vS[e] = sstat[(n0 + e / PL) * ss + e % PL];
-    if (EPI == 1)
-      for (int e = tid; e < BM; e += NT) Vs[e] = m0 + e < np ? Dv[m0 + e] : 0.0;
+#pragma unroll
+    for (int j = 0; j < JZ; ++j) {
+      const int e = tid + j * NT;
+      tz[j] = e < BM ? zs[m0 + e] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < JV; ++j) {
+      const int e = tid + j * NT;
+      tv[j] = e < BN * PL ? sstat[(n0 + e / PL) * ss + e % PL] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < JD; ++j) {
+      const int e = tid + j * NT;
+      td[j] = (e < BM && m0 + e < np) ? Dv[m0 + e] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < JQ; ++j)
+      if (tid + j * NT < BM * PL) Qs[tid + j * NT] = tq[j];
+#pragma unroll
+    for (int j = 0; j < JZ; ++j)
+      if (tid + j * NT < BM) zS[tid + j * NT] = tz[j];
+#pragma unroll
+    for (int j = 0; j < JV; ++j)
+      if (tid + j * NT < BN * PL) vS[tid + j * NT] = tv[j];
+#pragma unroll
+    for (int j = 0; j < JD; ++j)
+      if (tid + j * NT < BM) Vs[tid + j * NT] = td[j];
   };
 
   if constexpr (DL) {
@@ -234,10 +266,12 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
     using U1 = std::integral_constant<int, 1>;
     using U2 = std::integral_constant<int, 2>;
     using U3 = std::integral_constant<int, 3>;
+    // the first slices' loads go out before the tables', whose LDS writes
+    // wait for them
     issue(U0{}, 0);
-    load_tables();
     issue(U1{}, min(1, KT - 1));
     if constexpr (DL == 4) issue(U2{}, min(2, KT - 1));
+    load_tables();
     int kt = 0;
     for (; kt + DL <= KT; kt += DL) {
       step(U0{}, kt);
