@@ -102,15 +102,15 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   // slots, each its own LDS array so that the compiler can tell them apart
   static_assert(DL == 0 || DL == 3 || DL == 4, "ring depth");
   constexpr int FA = 8 * WR, FB = 2 * CT * WC, FS = FA + FB;
-  // slot 0 also holds the epilogue's per-wave-row partials (EPI 1), which can
-  // be larger than a slice
+  // slot 0 also holds the epilogue's per-wave-row partials of a (EPI 1); it is
+  // sized for them should they ever exceed a slice
   constexpr int PS_BYTES = EPI == 1 ? WR * BN * 8 : 0;
   constexpr int SMEM = DL ? (FS * 1024 > PS_BYTES ? FS * 1024 : PS_BYTES) : 2 * (A_STAGE + B_STAGE);
   __shared__ __attribute__((aligned(1024))) int8_t smem[SMEM];
   __shared__ __attribute__((aligned(1024))) int8_t smem1[DL ? FS * 1024 : 16];
   __shared__ __attribute__((aligned(1024))) int8_t smem2[DL ? FS * 1024 : 16];
   __shared__ __attribute__((aligned(1024))) int8_t smem3[DL == 4 ? FS * 1024 : 16];
-  // epilogue tables, fetched while the first stage loads
+  // epilogue tables, fetched while the first slices load
   constexpr int NTAB = BM * PL + BM + BN * PL + (EPI == 1 ? BM : 0);
   __shared__ double tab[NTAB];
   double* Qs = tab;             // [BM][PL]   (Z^T Q_L) rows of the tile
