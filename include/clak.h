@@ -235,12 +235,13 @@ typedef struct clak_batch_s* clak_batch_t;
 
 /* A reusable schedule of the per-block pipeline of `plan` over n_blocks
  * blocks (the same arithmetic as n_blocks calls of clak_run_block).  Blocks
- * alternate between two workspace slots so that the ingest of block b+1 runs
- * on a side stream while block b is rotated and reduced on the main stream.
+ * go round three workspace slots so that the ingest of blocks b+1 and b+2
+ * runs on a side stream while block b is rotated and reduced; consecutive
+ * blocks alternate between two compute streams.
  * The block arguments are validated and copied at creation; the buffers they
  * point to must stay valid, and the plan must keep its workspace, while the
  * pipeline is launched.  New traits (clak_set_traits) or covariates are picked
- * up by later launches.  Creates two streams and a few events; no device work.
+ * up by later launches.  Creates three streams and a few events; no device work.
  * Errors: as clak_run_block, CLAK_E_DEVICE. */
 clak_status clak_pipeline_create(clak_pipeline_t* pipe, clak_plan_t plan, int64_t n_blocks,
                                  const clak_block* blocks, int g_dtype, int out_dtype);
@@ -300,7 +301,7 @@ clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int 
  * bytes 0x6c 0x1b 0x01, then m rows of (n + 3) / 4 bytes in the CLAK_G_P2
  * coding) is read block by block by a host thread into `depth` (2 to 16)
  * pinned host buffers of `block` rows; clak_bed_scan streams the blocks
- * through the plan's two-slot pipeline as they arrive (the ingest reads each
+ * through the plan's block pipeline as they arrive (the ingest reads each
  * block from pinned memory over PCIe, or through the copy engine with
  * CLAK_STAGE_GENOTYPES), so disk reads, transfers and kernels overlap; a
  * buffer is refilled once the ingest that read it has completed.  The blocks

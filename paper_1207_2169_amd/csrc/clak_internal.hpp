@@ -77,7 +77,9 @@ struct Slot {
   int8_t* Xd = nullptr;
   uint8_t* Gh = nullptr;  // CLAK_STAGE_GENOTYPES: copy of the caller's genotype block, rows of host_pitch bytes
 };
-constexpr int NSLOTS = 2;
+// Workspace slots of the block pipeline: the ingest of block b reuses slot
+// b % NSLOTS once block b - NSLOTS has finished.
+constexpr int NSLOTS = 3;
 
 // Row pitch (bytes) of the host-block staging buffer: n elements of up to 2 bytes, 16-byte aligned rows.
 inline int64_t host_pitch(int64_t n) { return (2 * n + 15) / 16 * 16; }

@@ -2,16 +2,21 @@
 // (clak_pipeline_*), and several plans (cohorts) in one submission
 // (clak_batch_*).
 //
-// Within a plan, blocks alternate between the two workspace slots: block b is
-// ingested on a side stream into slot b % 2 (after block b - 2, the previous
-// user of that slot, has finished) while block b - 1 is rotated and reduced,
-// so the memory-bound ingest overlaps the MFMA-bound rotation.  Each slot has
-// its own compute stream, so the kernels of block b + 1 start while the last
-// work-groups of block b drain (every buffer a block writes belongs to its
-// slot or to its own outputs); with the stage profiler on, one compute stream
-// serves both slots so that per-kernel times are not shared.  A launch enqueues the whole schedule from the host: the side and
-// main streams are forked from the launch stream by an event and joined back
-// to it at the end, so the launch stream sees the pipeline as one unit of work.
+// Within a plan, blocks go round the NSLOTS (three) workspace slots: block b
+// is ingested on a side stream into slot b % 3 once block b - 3, the previous
+// user of that slot, has finished, so the ingest runs up to two blocks ahead
+// of the rotation and the memory-bound ingest overlaps the MFMA-bound
+// rotation without waiting on the block just before.  Blocks alternate
+// between two compute streams, so the kernels of block b + 1 start while the
+// last work-groups of block b drain (every buffer a block writes belongs to
+// its slot or to its own outputs; a slot is reused only after the wait on its
+// last user, whichever stream ran it).  Two compute streams and the side
+// stream, with the launch stream, stay within four hardware queues.  With the
+// stage profiler on, one compute stream serves every block so that
+// per-kernel times are not shared.  A launch enqueues the whole schedule from
+// the host: the side and compute streams are forked from the launch stream by
+// an event and joined back to it at the end, so the launch stream sees the
+// pipeline as one unit of work.
 // Cohorts of a batch get their own stream pairs and run concurrently.
 #include <functional>
 #include <vector>
@@ -22,12 +27,14 @@ using namespace clak;
 
 namespace {
 
+constexpr int NCOMPUTE = 2;  // compute streams per plan
+
 struct PlanStreams {
   Plan* plan = nullptr;
-  hipStream_t s_main[NSLOTS] = {nullptr, nullptr}, s_in = nullptr;
-  hipEvent_t ingested[NSLOTS] = {nullptr, nullptr};
-  hipEvent_t done[NSLOTS] = {nullptr, nullptr};
-  hipEvent_t joined_in = nullptr, joined_main[NSLOTS] = {nullptr, nullptr};
+  hipStream_t s_main[NCOMPUTE] = {}, s_in = nullptr;
+  hipEvent_t ingested[NSLOTS] = {};
+  hipEvent_t done[NSLOTS] = {};
+  hipEvent_t joined_in = nullptr, joined_main[NCOMPUTE] = {};
   int64_t first = 0, count = 0;  // blocks [first, first + count) of the block list
 };
 
@@ -41,12 +48,14 @@ struct Schedule {
 void release(Schedule* g) {
   if (!g) return;
   for (auto& c : g->ps) {
-    for (int k = 0; k < NSLOTS; ++k)
+    for (int k = 0; k < NCOMPUTE; ++k)
       if (c.s_main[k]) (void)hipStreamSynchronize(c.s_main[k]);
     if (c.s_in) (void)hipStreamSynchronize(c.s_in);
     for (int k = 0; k < NSLOTS; ++k) {
       if (c.ingested[k]) (void)hipEventDestroy(c.ingested[k]);
       if (c.done[k]) (void)hipEventDestroy(c.done[k]);
+    }
+    for (int k = 0; k < NCOMPUTE; ++k) {
       if (c.joined_main[k]) (void)hipEventDestroy(c.joined_main[k]);
       if (c.s_main[k]) (void)hipStreamDestroy(c.s_main[k]);
     }
@@ -57,11 +66,11 @@ void release(Schedule* g) {
   delete g;
 }
 
-// The compute stream of a slot.  While the stage profiler runs, both slots
-// share one, so that each kernel's bracketed time is its own (consecutive
-// blocks do not overlap); the ingest still overlaps on its side stream.
-hipStream_t compute_stream(const Plan* p, const PlanStreams& c, int slot) {
-  return p->profiling ? c.s_main[0] : c.s_main[slot];
+// The compute stream of block j.  While the stage profiler runs, every block
+// uses one, so that each kernel's bracketed time is its own (consecutive
+// blocks do not overlap).
+hipStream_t compute_stream(const Plan* p, const PlanStreams& c, int64_t j) {
+  return p->profiling ? c.s_main[0] : c.s_main[j % NCOMPUTE];
 }
 
 #define CK(expr, what)                                                                      \
@@ -83,11 +92,13 @@ clak_status make_schedule(Schedule* g, const std::vector<Plan*>& plans, const st
     c.first = off[k];
     c.count = off[k + 1] - off[k];
     CK(hipStreamCreateWithFlags(&c.s_in, hipStreamNonBlocking), what);
-    for (int q = 0; q < NSLOTS; ++q) {
+    for (int q = 0; q < NCOMPUTE; ++q) {
       CK(hipStreamCreateWithFlags(&c.s_main[q], hipStreamNonBlocking), what);
+      CK(hipEventCreateWithFlags(&c.joined_main[q], hipEventDisableTiming), what);
+    }
+    for (int q = 0; q < NSLOTS; ++q) {
       CK(hipEventCreateWithFlags(&c.ingested[q], hipEventDisableTiming), what);
       CK(hipEventCreateWithFlags(&c.done[q], hipEventDisableTiming), what);
-      CK(hipEventCreateWithFlags(&c.joined_main[q], hipEventDisableTiming), what);
     }
     CK(hipEventCreateWithFlags(&c.joined_in, hipEventDisableTiming), what);
   }
@@ -100,12 +111,12 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
   for (auto& c : g->ps) {
     Plan* p = c.plan;
     // compute streams this launch uses (one for a single block or while profiling)
-    const int nmain = (p->profiling || c.count < 2) ? 1 : NSLOTS;
+    const int nmain = (p->profiling || c.count < 2) ? 1 : NCOMPUTE;
     for (int q = 0; q < nmain; ++q) CK(hipStreamWaitEvent(c.s_main[q], g->fork, 0), what);
     CK(hipStreamWaitEvent(c.s_in, g->fork, 0), what);
     for (int64_t j = 0; j < c.count; ++j) {
       const int slot = (int)(j % NSLOTS);
-      const hipStream_t sm = compute_stream(p, c, slot);
+      const hipStream_t sm = compute_stream(p, c, j);
       // while profiling the ingest runs on the compute stream too, so that
       // every stage is timed without a concurrent kernel
       const hipStream_t si = p->profiling ? sm : c.s_in;
@@ -139,8 +150,8 @@ clak_status check_blocks(Plan* p, int64_t n, const clak_block* blocks, int g_dty
 
 namespace clak {
 
-// Streams n_blocks blocks of one plan through the two-slot, per-slot-stream
-// schedule of a pipeline, asking `get` for each block just before it is
+// Streams n_blocks blocks of one plan through the slot ring and compute
+// streams of a pipeline, asking `get` for each block just before it is
 // enqueued (it may wait, e.g. for a file read) and calling `after` with the
 // ingest stream once the block's ingest is enqueued (e.g. to record when its
 // input buffer may be reused).  Forked from and joined back to the plan's
@@ -161,7 +172,7 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
     return e == hipSuccess ? CLAK_OK : fail(CLAK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
   };
   if ((s = ck(hipEventRecord(g->fork, p->stream)))) return done(s);
-  for (int q = 0; q < NSLOTS; ++q)
+  for (int q = 0; q < NCOMPUTE; ++q)
     if ((s = ck(hipStreamWaitEvent(c.s_main[q], g->fork, 0)))) return done(s);
   if ((s = ck(hipStreamWaitEvent(c.s_in, g->fork, 0)))) return done(s);
   clak_status result = CLAK_OK;
@@ -170,7 +181,7 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
     clak_block B{};
     if ((result = get(j, &B))) break;
     if ((result = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval))) break;
-    const hipStream_t sm = compute_stream(p, c, slot);
+    const hipStream_t sm = compute_stream(p, c, j);
     const hipStream_t si = p->profiling ? sm : c.s_in;  // as in run_schedule
     if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(si, c.done[slot], 0)))) break;
     if ((result = enqueue_block(p, slot, si, sm, c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
@@ -182,7 +193,7 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
   // join everything enqueued so far back to the plan's stream and wait for it
   clak_status js = ck(hipEventRecord(c.joined_in, c.s_in));
   if (!js) js = ck(hipStreamWaitEvent(p->stream, c.joined_in, 0));
-  for (int q = 0; q < NSLOTS && !js; ++q) {
+  for (int q = 0; q < NCOMPUTE && !js; ++q) {
     js = ck(hipEventRecord(c.joined_main[q], c.s_main[q]));
     if (!js) js = ck(hipStreamWaitEvent(p->stream, c.joined_main[q], 0));
   }
