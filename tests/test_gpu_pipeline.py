@@ -125,17 +125,20 @@ def test_batch_of_uneven_cohorts_matches_per_plan():
             p.close()
 
 
-@pytest.mark.parametrize("prec,t", [(1, 1), (1, 7), (0, 1), (0, 7)])
-def test_two_stream_pipeline_matches_eager(prec, t):
-    """The two-stream pipeline (slots alternate, ingest overlapped) gives
-    bitwise the outputs of eager clak_run_block calls, over repeated launches
-    with eager work in between."""
+@pytest.mark.parametrize("prec,t,m", [(1, 1, 900), (1, 7, 900), (0, 1, 900), (0, 7, 900), (1, 1, 3000),
+                                      (1, 7, 3000), (0, 1, 3000)])
+def test_two_stream_pipeline_matches_eager(prec, t, m):
+    """The pipeline (blocks round the workspace slots, alternating between two
+    compute streams, ingest overlapped) gives bitwise the outputs of eager
+    clak_run_block calls, over repeated launches with eager work in between.
+    m = 3000 makes 12 blocks of 256 (the last ragged): every slot is reused
+    several times, by either compute stream."""
     import torch
 
     from paper_1207_2169_amd import clak
-    w = make_workload(2, n=300, m=900, t=t, kin_cols=600)
-    block = 256  # 4 blocks, the last ragged
-    print(f"two-stream pipeline prec={prec} t={t}", flush=True)
+    w = make_workload(2, n=300, m=m, t=t, kin_cols=600)
+    block = 256
+    print(f"two-stream pipeline prec={prec} t={t} m={m}", flush=True)
     with _setup(w, prec, block) as plan:
         G, b, se, fl, blocks = _blocks(w, block, torch.float64)
         _eager(plan, blocks)
