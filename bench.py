@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--m", type=int, default=None, help="override the number of SNPs (a multiple of the block)")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64-path comparison run")
     ap.add_argument("--eager", action="store_true",
-                    help="call clak_run_block per block on one stream instead of the two-stream pipeline")
+                    help="call clak_run_block per block on one stream instead of the block pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-genotypes", action="store_true",
                     help="keep the genotypes in pinned host memory: the ingest kernel reads them over PCIe "
@@ -93,8 +93,9 @@ def block_list(G, b, se, block, pv=None):
 
 
 class Pass:
-    """One step: every block of the workload, through the two-stream pipeline
-    (ingest of block b+1 overlapped with block b) or per-block calls."""
+    """One step: every block of the workload, through the block pipeline
+    (ingest of the next blocks on a side stream overlapped with block b,
+    blocks alternating between two compute streams) or per-block calls."""
 
     def __init__(self, clak, plan, G, b, se, block, eager, pv=None):
         self.clak, self.plan, self.eager = clak, plan, eager
@@ -414,7 +415,7 @@ def main():
 def run_cohorts(args, clak, torch):
     """The batched configuration: eight cohorts of uneven n and t, each a plan
     with its own kinship eigendecomposition, submitted as one clak_batch
-    launch (every cohort a two-stream pipeline over its SNP blocks, the
+    launch (every cohort a block pipeline over its SNP blocks, the
     cohorts concurrent).  A step is one launch over all cohorts."""
     from synth import cohort_workloads
     _, wname = WORKLOADS["c3"]
@@ -478,7 +479,7 @@ def run_cohorts(args, clak, torch):
                      "basis": "rotation and grid flops of all cohorts per step / wall time of the step",
                      "peak_source": peak_name},
         "stage_ms_summed_over_cohorts": {k: sum(p[k][0] for p in profs) / args.steps for k in profs[0]},
-        "launch": "clak_batch_launch: one pipeline per cohort on its own stream pair, cohorts concurrent",
+        "launch": "clak_batch_launch: one pipeline per cohort on its own streams, cohorts concurrent",
         "setup_ms": setup,
     }
     if not args.no_cpu_baseline:

@@ -1,5 +1,5 @@
 """Parity at the full workload sizes in the launch configuration the benchmark
-times (the two-stream pipeline over every SNP block, FP32 outputs), on cells
+times (the block pipeline over every SNP block, FP32 outputs), on cells
 sampled uniformly and at block edges and checked one by one against the
 oracle; and the large configuration (n = 10^4, p_L = 8 with five principal
 components) on one block.
