@@ -255,7 +255,7 @@ clak_status clak_pipeline_destroy(clak_pipeline_t pipe);
 
 /* Several cohorts in one submission: plans[k] (distinct plans, each READY, on
  * the same device) runs its n_blocks[k] blocks, taken consecutively from
- * `blocks`, as a pipeline on its own stream pair; the cohorts run
+ * `blocks`, as a pipeline on its own three streams; the cohorts run
  * concurrently, so the hardware scheduler balances cohorts of uneven n and t.
  * Same lifetime rules as a pipeline. */
 clak_status clak_batch_create(clak_batch_t* batch, int n_plans, const clak_plan_t* plans, const int64_t* n_blocks,

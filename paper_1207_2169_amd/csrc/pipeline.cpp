@@ -17,7 +17,7 @@
 // the host: the side and compute streams are forked from the launch stream by
 // an event and joined back to it at the end, so the launch stream sees the
 // pipeline as one unit of work.
-// Cohorts of a batch get their own stream pairs and run concurrently.
+// Cohorts of a batch get their own streams and run concurrently.
 #include <functional>
 #include <vector>
 
