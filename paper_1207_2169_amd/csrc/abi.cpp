@@ -681,22 +681,27 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   const int pow2[4] = {1, 2, 4, 8};
   p->rot_cfg = 0;
   p->rot_rg = 0;
-  float best_t = MARGIN * time_ms([&] { return launch_rotate_snps(*p, m_blk); });
   int best_cfg = 0, best_rg = 0;
-  for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
-    for (int rg : pow2) {
-      p->rot_cfg = cfg;
-      p->rot_rg = rg;
-      const float ms = time_ms([&] { return launch_rotate_snps(*p, m_blk); });
-      if (ms < best_t) best_t = ms, best_cfg = cfg, best_rg = rg;
-    }
+  // the built-in wide tiles of single-trait CLAK-Eig plans are chosen for the
+  // block pipeline, where they are faster although a launch alone is slower,
+  // so launches timed alone do not replace them
+  if (!rot_wide_builtin(*p)) {
+    float best_t = MARGIN * time_ms([&] { return launch_rotate_snps(*p, m_blk); });
+    for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
+      for (int rg : pow2) {
+        p->rot_cfg = cfg;
+        p->rot_rg = rg;
+        const float ms = time_ms([&] { return launch_rotate_snps(*p, m_blk); });
+        if (ms < best_t) best_t = ms, best_cfg = cfg, best_rg = rg;
+      }
+  }
   p->rot_cfg = best_cfg;
   p->rot_rg = best_rg;
   int best_tt = 0, best_xt = 0;
   if (tune_grid) {
     p->grid_tt = 0;
     p->grid_xt = 0;
-    best_t = MARGIN * time_ms([&] { return launch_grid(*p, m_blk, out); });
+    float best_t = MARGIN * time_ms([&] { return launch_grid(*p, m_blk, out); });
     for (int tt : {32, 64})
       for (int xt : pow2) {
         p->grid_tt = tt;

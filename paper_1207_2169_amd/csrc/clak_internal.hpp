@@ -181,6 +181,18 @@ constexpr int64_t ZEXT = 64;  // rows of the extra rotation tile (one 64-row til
 // rows; its other rows give only the quadratic sum a.
 inline bool lin_rows(const Plan& p) { return p.fused_t1 && p.prec == CLAK_PREC_MIXED; }
 
+// The built-in rotation tiles of the mixed path (rot_cfg 0): 64 x 256 SNPs
+// (configuration 6) for single-trait CLAK-Eig plans over blocks of at least
+// ROT_WIDE_MIN SNPs, else 64 x 128.  Measured at n = 1000 with blocks of
+// 10^4 SNPs, a 64 x 256 launch alone is slower (55 against 50 us), but the
+// block pipeline, where consecutive rotations overlap each other and the
+// ingest, runs faster with it (5.07 against 5.66 ms per 10^6 SNPs); at 2000
+// SNPs in one block the 64 x 128 tiles are faster.
+constexpr int64_t ROT_WIDE_MIN = 8192;
+inline bool rot_wide_builtin(const Plan& p) {
+  return lin_rows(p) && !(p.flags & CLAK_CHOL) && p.mb_pad >= ROT_WIDE_MIN;
+}
+
 // Points the per-block buffers of the workspace at slot k.
 inline void select_slot(Plan& p, int k) {
   const Slot& s = p.ws.slot[k];

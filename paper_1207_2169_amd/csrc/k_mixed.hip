@@ -595,7 +595,7 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
 }
 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
-  switch (p.rot_cfg) {
+  switch (p.rot_cfg ? p.rot_cfg : (rot_wide_builtin(p) ? 6 : 0)) {
     case 1:
       return rotate_cfg<4, 2, 1, 0>(p, m_blk);
     case 2:
