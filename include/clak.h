@@ -278,7 +278,10 @@ clak_status clak_batch_destroy(clak_batch_t batch);
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
  *   grid_tt : traits per work-group of the grid contraction (32 or 64);
  *   grid_xt : XCD trait groups of the grid contraction (1, 2, 4, 8).
- * 0 selects the built-in choice.  Errors: CLAK_E_ARG for other values. */
+ * 0 selects the built-in choice: for the rotation, 64 x 256 tiles
+ * (configuration 6) in single-trait CLAK-Eig plans whose blocks hold at least
+ * 8192 SNPs (slower per launch alone, faster in the block pipeline), else
+ * 64 x 128 tiles; XCD row groups 2.  Errors: CLAK_E_ARG for other values. */
 clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
 /* The launch parameters in effect (0: built-in choice); null outputs skipped. */
@@ -288,8 +291,10 @@ clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, in
  * block size.  With a readable cache_path holding a line for the shape
  * (device, n_pad, p_L, t, m_blk) its choice is applied; otherwise every
  * candidate of clak_plan_set_tuning is timed with HIP events on this block
- * (three launches each of the rotation and, with several traits, of the grid
- * kernel unless CLAK_OUT_FULL with p_L > 3), the fastest kept in the plan and, when cache_path is
+ * (three launches each of the rotation, unless the plan takes the built-in
+ * 64 x 256 tiles, which are chosen for the pipeline, and, with several traits,
+ * of the grid kernel unless CLAK_OUT_FULL with p_L > 3), a candidate kept in
+ * the plan only when more than 3 % faster than the built-in choice and, when cache_path is
  * not NULL, appended to that text file ("<shape> rot_cfg=C rot_rg=R
  * grid_tt=T grid_xt=X").  The block's outputs are then computed with the
  * chosen parameters, as by clak_run_block (without p-values).  Synchronous.  The FP64 path has nothing
