@@ -682,9 +682,9 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   p->rot_cfg = 0;
   p->rot_rg = 0;
   int best_cfg = 0, best_rg = 0;
-  // the built-in wide tiles of single-trait CLAK-Eig plans are chosen for the
-  // block pipeline, where they are faster although a launch alone is slower,
-  // so launches timed alone do not replace them
+  // the built-in wide tiles of single-trait plans are chosen for the block
+  // pipeline, where they are faster although a launch alone is slower, so
+  // launches timed alone do not replace them
   if (!rot_wide_builtin(*p)) {
     float best_t = MARGIN * time_ms([&] { return launch_rotate_snps(*p, m_blk); });
     for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)

@@ -182,16 +182,18 @@ constexpr int64_t ZEXT = 64;  // rows of the extra rotation tile (one 64-row til
 inline bool lin_rows(const Plan& p) { return p.fused_t1 && p.prec == CLAK_PREC_MIXED; }
 
 // The built-in rotation tiles of the mixed path (rot_cfg 0): 64 x 256 SNPs
-// (configuration 6) for single-trait CLAK-Eig plans over blocks of at least
+// (configuration 6) for single-trait plans over blocks of at least
 // ROT_WIDE_MIN SNPs, else 64 x 128.  Measured at n = 1000 with blocks of
 // 10^4 SNPs, a 64 x 256 launch alone is slower (55 against 50 us), but the
 // block pipeline, where consecutive rotations overlap each other and the
-// ingest, runs faster with it (5.07 against 5.66 ms per 10^6 SNPs); at 2000
-// SNPs in one block the 64 x 128 tiles are faster.
+// ingest, runs faster with it (CLAK-Eig 5.07 against 5.66 ms per 10^6 SNPs,
+// CLAK-Chol 4.01 against 5.06 ms); at 2000 SNPs in one block the 64 x 128
+// tiles are faster.
 constexpr int64_t ROT_WIDE_MIN = 8192;
-inline bool rot_wide_builtin(const Plan& p) {
-  return lin_rows(p) && !(p.flags & CLAK_CHOL) && p.mb_pad >= ROT_WIDE_MIN;
-}
+inline bool rot_wide_builtin(const Plan& p) { return lin_rows(p) && p.mb_pad >= ROT_WIDE_MIN; }
+// Built-in XCD row groups of the rotation: 1 for CLAK-Chol's triangular
+// operand with the wide tiles (4.01 against 4.26 ms per 10^6 SNPs), else 2.
+inline int rot_rg_builtin(const Plan& p) { return (rot_wide_builtin(p) && (p.flags & CLAK_CHOL)) ? 1 : 2; }
 
 // Points the per-block buffers of the workspace at slot k.
 inline void select_slot(Plan& p, int k) {

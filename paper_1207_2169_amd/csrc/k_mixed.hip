@@ -58,8 +58,6 @@ __device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
 }
 
-constexpr int ROT_RG_DEFAULT = 2;  // XCD grid: rg row groups x 8 / rg SNP groups
-
 // Waves per SIMD the register budget is cut for: three for the one-column-tile
 // configuration (64 accumulation registers), else one or two.
 template <int PL, int EPI, int CT>
@@ -563,7 +561,7 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   static_assert(32 * WR == ROT_BM && SNP_PAD % BN == 0, "rotation tile");
   const Workspace& W = p.ws;
   const int64_t ntn = roundup(m_blk, SNP_PAD) / BN, ntm = p.zrows / ROT_BM;
-  const int rg = p.rot_rg ? p.rot_rg : ROT_RG_DEFAULT;
+  const int rg = p.rot_rg ? p.rot_rg : rot_rg_builtin(p);  // XCD grid: rg row groups x 8 / rg SNP groups
   const int tri = (p.flags & CLAK_CHOL) ? 1 : 0;
   const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
   dim3 grid((unsigned)(8 * gm * gn));

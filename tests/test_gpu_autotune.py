@@ -89,20 +89,21 @@ def test_autotune_matches_run_block_and_uses_cache(tmp_path):
             assert torch.equal(a, r)
 
 
-# Single-trait CLAK-Eig plans over blocks of at least 8192 SNPs take 64 x 256
-# rotation tiles by default.  n = 126 (p_L = 3) and n = 1020 (p_L = 8) put the
+# Single-trait plans over blocks of at least 8192 SNPs take 64 x 256 rotation
+# tiles by default (CLAK-Chol's triangular ones with one XCD row group).  n = 126 (p_L = 3) and n = 1020 (p_L = 8) put the
 # U^T rows in the extra 64-row tile; n = 1000 keeps them in the padding rows.
 # The default must equal, bitwise, the 64 x 128 configurations (the
 # register-staged one and the four-slot ring) and a 64 x 64 one, over a full
 # block and a ragged one.
-@pytest.mark.parametrize("n,config", [(126, 2), (1000, 2), (1000, 4), (1020, 4)])
-def test_wide_default_rotation_is_bitwise_identical(n, config):
+@pytest.mark.parametrize("n,config,chol", [(126, 2, False), (1000, 2, False), (1000, 4, False), (1020, 4, False),
+                                          (126, 2, True), (1000, 2, True)])
+def test_wide_default_rotation_is_bitwise_identical(n, config, chol):
     import torch
 
     from paper_1207_2169_amd import clak
     block = 8192
     w = make_workload(config, n=n, m=block + 300, t=1, kin_cols=2 * n)
-    print(f"wide default rotation n={n} p_L={w.pL}", flush=True)
+    print(f"wide default rotation n={n} p_L={w.pL} chol={chol}", flush=True)
     G = torch.from_numpy(w.genotypes(0, w.m)).cuda()
 
     def run(plan):
@@ -112,7 +113,7 @@ def test_wide_default_rotation_is_bitwise_identical(n, config):
         torch.cuda.synchronize()
         return out
 
-    with _plan(w, block) as plan:
+    with _plan(w, block, clak.CLAK_CHOL if chol else 0) as plan:
         ref = run(plan)
         assert bool(torch.isfinite(ref[0]).all()) and bool((ref[2] == 0).all())
         for cfg in (5, 9, 7):
