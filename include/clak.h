@@ -279,9 +279,10 @@ clak_status clak_batch_destroy(clak_batch_t batch);
  *   grid_tt : traits per work-group of the grid contraction (32 or 64);
  *   grid_xt : XCD trait groups of the grid contraction (1, 2, 4, 8).
  * 0 selects the built-in choice: for the rotation, 64 x 256 tiles
- * (configuration 6) in single-trait CLAK-Eig plans whose blocks hold at least
- * 8192 SNPs (slower per launch alone, faster in the block pipeline), else
- * 64 x 128 tiles; XCD row groups 2.  Errors: CLAK_E_ARG for other values. */
+ * (configuration 6) in single-trait plans whose blocks hold at least 8192
+ * SNPs (slower per launch alone, faster in the block pipeline), with one XCD
+ * row group under CLAK_CHOL and two otherwise, else 64 x 128 tiles and two
+ * row groups.  Errors: CLAK_E_ARG for other values. */
 clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
 /* The launch parameters in effect (0: built-in choice); null outputs skipped. */
