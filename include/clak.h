@@ -285,6 +285,13 @@ clak_status clak_batch_destroy(clak_batch_t batch);
  * row groups.  Errors: CLAK_E_ARG for other values. */
 clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
+/* The sizes and options the plan was created with (n, p_L, t, max_block,
+ * precision, flags of clak_plan_create); null outputs are skipped.  Lets a
+ * binding check the shapes of the tensors it passes against the plan before
+ * any call that reads or writes them.  Errors: CLAK_E_ARG (null plan). */
+clak_status clak_plan_get_shape(clak_plan_t plan, int64_t* n, int64_t* p_L, int64_t* t, int64_t* max_block,
+                                int* precision, uint32_t* flags);
+
 /* The launch parameters in effect (0: built-in choice); null outputs skipped. */
 clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, int* grid_tt, int* grid_xt);
 
@@ -339,19 +346,35 @@ clak_status clak_bed_close(clak_bed_t bed);
 #define CLAK_STAGE_GRID 3    /* grid contraction + Schur solve, or the single-trait finish */
 #define CLAK_STAGE_COUNT 4
 
-/* Turns per-stage timing on (enable != 0) or off and clears the
- * accumulators.  While on, clak_run_block brackets each stage's kernel with
- * HIP events on the stream it runs on (a little host overhead per launch),
- * and pipelines, batches and file scans run every kernel of consecutive
- * blocks, the ingest included, on one stream, so that no two of them overlap
- * and each bracketed time is that kernel's own. */
-clak_status clak_plan_set_profiling(clak_plan_t plan, int enable);
+/* Stage profiler modes. */
+#define CLAK_PROFILE_OFF 0
+#define CLAK_PROFILE_SERIAL 1     /* every kernel alone: its own duration      */
+#define CLAK_PROFILE_PIPELINED 2  /* kernels as the pipeline overlaps them     */
 
-/* Waits for the plan's stream, then returns per stage the summed kernel time
- * in milliseconds (ms[CLAK_STAGE_COUNT]) and the number of launches timed
+/* Turns per-stage timing on in the given mode (CLAK_PROFILE_SERIAL or
+ * CLAK_PROFILE_PIPELINED) or off (CLAK_PROFILE_OFF) and clears the
+ * accumulators.  While on, clak_run_block brackets each stage's kernel with
+ * HIP events on the stream it runs on (a little host overhead per launch).
+ * SERIAL: pipelines, batches and file scans run every kernel of consecutive
+ * blocks, the ingest included, on one stream, so that no two of them overlap
+ * and each bracketed time is that kernel's own.  PIPELINED: they keep their
+ * streams, so each bracketed time is the launch's duration as the pipeline
+ * runs it (overlapping the ingest and the other compute stream's kernels).
+ * Errors: CLAK_E_ARG (null plan, unknown mode), CLAK_E_DEVICE. */
+clak_status clak_plan_set_profiling(clak_plan_t plan, int mode);
+
+/* Waits for the device, then returns per stage the summed kernel time in
+ * milliseconds (ms[CLAK_STAGE_COUNT]) and the number of launches timed
  * (launches[CLAK_STAGE_COUNT]) since profiling was last enabled.  Either
  * array may be NULL. */
 clak_status clak_plan_get_profile(clak_plan_t plan, double* ms, int64_t* launches);
+
+/* Waits for the device, then returns per stage (busy[CLAK_STAGE_COUNT]) the
+ * time in milliseconds during which at least one of the stage's timed launches
+ * ran since profiling was last enabled: the length of the union of their
+ * intervals, which never exceeds the wall time of the work timed (unlike the
+ * sum of overlapping launches).  Errors: CLAK_E_ARG, CLAK_E_DEVICE. */
+clak_status clak_plan_get_busy(clak_plan_t plan, double* busy);
 
 /* Destroys the plan (host memory, rocBLAS handle).  Never frees the workspace. */
 clak_status clak_plan_destroy(clak_plan_t plan);

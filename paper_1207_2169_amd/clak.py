@@ -15,8 +15,9 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional
+from typing import NamedTuple, Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,6 +37,7 @@ CLAK_VC_ML, CLAK_VC_REML = 0, 1
 CLAK_CELL_OK, CLAK_CELL_DEGENERATE, CLAK_CELL_BAD_GENOTYPE = 0, 1, 2
 CLAK_STAGE_INGEST, CLAK_STAGE_ROTATE, CLAK_STAGE_ENCODE, CLAK_STAGE_GRID, CLAK_STAGE_COUNT = 0, 1, 2, 3, 4
 STAGE_NAMES = ("ingest", "rotate", "encode", "grid")
+CLAK_PROFILE_OFF, CLAK_PROFILE_SERIAL, CLAK_PROFILE_PIPELINED = 0, 1, 2
 
 # exported symbol -> (restype, argtypes)
 _P, _I64, _I, _U32, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
@@ -54,8 +56,10 @@ SIGNATURES = {
     "clak_plan_set_profiling": (_I, [_P, _I]),
     "clak_plan_set_tuning": (_I, [_P, _I, _I, _I, _I]),
     "clak_plan_get_tuning": (_I, [_P, _P, _P, _P, _P]),
+    "clak_plan_get_shape": (_I, [_P, _P, _P, _P, _P, _P, _P]),
     "clak_autotune": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, ctypes.c_char_p]),
     "clak_plan_get_profile": (_I, [_P, _P, _P]),
+    "clak_plan_get_busy": (_I, [_P, _P]),
     "clak_bed_open": (_I, [ctypes.POINTER(_P), ctypes.c_char_p, _I64, _I64, _I64, _I]),
     "clak_bed_scan": (_I, [_P, _P, _P, _P, _I, _I64, _P, _P]),
     "clak_bed_close": (_I, [_P]),
@@ -80,6 +84,7 @@ SIGNATURES.update({
 })
 
 _lib_handle = None
+_BED_SNPS = {}  # SNPs of each open genotype file reader (outputs are checked against it)
 
 
 class ClakError(RuntimeError):
@@ -119,17 +124,52 @@ def _dev(x: torch.Tensor, what: str, dtype=None):
     return x
 
 
-def _colmajor(A: torch.Tensor, what: str):
-    """(pointer, leading dimension, keep-alive tensor) of an n x c matrix."""
-    _dev(A, what, torch.float64)
+def _colmajor_view(A: torch.Tensor, what: str, shape=None):
+    """(A', ld): A as an n x c column-major matrix the library can read with
+    leading dimension ld (a copy when A's rows are not unit-strided, whatever
+    its number of columns), after checking its shape against `shape`."""
     if A.dim() == 1:
         A = A.reshape(-1, 1)
     if A.dim() != 2:
         raise ValueError(f"{what} must be 2-D")
-    if A.stride(0) != 1 and A.shape[1] > 1:
+    if shape is not None and tuple(A.shape) != tuple(shape):
+        raise ValueError(f"{what} must have shape {tuple(shape)}, got {tuple(A.shape)}")
+    if (A.shape[0] > 1 and A.stride(0) != 1) or (A.shape[1] > 1 and A.stride(1) < A.shape[0]):
         A = A.t().contiguous().t()
     ld = A.stride(1) if A.shape[1] > 1 else A.shape[0]
-    return A.data_ptr(), max(ld, A.shape[0]), A
+    return A, max(ld, A.shape[0])
+
+
+def _colmajor(A: torch.Tensor, what: str, shape=None):
+    """(pointer, leading dimension, keep-alive tensor) of an n x c matrix."""
+    _dev(A, what, torch.float64)
+    A, ld = _colmajor_view(A, what, shape)
+    return A.data_ptr(), ld, A
+
+
+def _vector(x: torch.Tensor, what: str, count: int):
+    """A contiguous float64 device vector of exactly `count` values."""
+    x = _dev(x, what, torch.float64)
+    if x.dim() != 1 or x.numel() != count:
+        raise ValueError(f"{what} must be a 1-D tensor of {count} values, got shape {tuple(x.shape)}")
+    return x.contiguous()
+
+
+class Shape(NamedTuple):
+    """The sizes and options of a plan (the arguments of clak_plan_create)."""
+    n: int
+    p_L: int
+    t: int
+    max_block: int
+    precision: int = CLAK_PREC_FP64
+    flags: int = 0
+
+
+def clak_plan_get_shape(plan: int) -> Shape:
+    """The sizes and options the plan was created with."""
+    v = [ctypes.c_int64(0) for _ in range(4)] + [ctypes.c_int(0), ctypes.c_uint32(0)]
+    _check(lib().clak_plan_get_shape(plan, *[ctypes.cast(ctypes.byref(x), _P) for x in v]), "clak_plan_get_shape")
+    return Shape(*(x.value for x in v))
 
 
 def clak_version() -> str:
@@ -162,40 +202,45 @@ def clak_plan_set_stream(plan: int, stream: Optional[torch.cuda.Stream] = None):
 
 
 def clak_set_kinship(plan: int, Phi: torch.Tensor):
-    ptr, ld, _keep = _colmajor(Phi, "Phi")
+    n = clak_plan_get_shape(plan).n
+    ptr, ld, _keep = _colmajor(Phi, "Phi", (n, n))
     _check(lib().clak_set_kinship(plan, ptr, ld), "clak_set_kinship")
 
 
 def clak_set_eigen(plan: int, Z: torch.Tensor, w: torch.Tensor):
-    ptr, ld, _keep = _colmajor(Z, "Z")
-    w = _dev(w, "w", torch.float64).contiguous()
+    n = clak_plan_get_shape(plan).n
+    ptr, ld, _keep = _colmajor(Z, "Z", (n, n))
+    w = _vector(w, "w", n)
     _check(lib().clak_set_eigen(plan, ptr, ld, w.data_ptr()), "clak_set_eigen")
 
 
 def clak_set_covariates(plan: int, XL: torch.Tensor):
-    ptr, ld, _keep = _colmajor(XL, "X_L")
+    sh = clak_plan_get_shape(plan)
+    ptr, ld, _keep = _colmajor(XL, "X_L", (sh.n, sh.p_L))
     _check(lib().clak_set_covariates(plan, ptr, ld), "clak_set_covariates")
 
 
 def clak_set_traits(plan: int, Y: torch.Tensor, h2: torch.Tensor, s2: torch.Tensor):
-    ptr, ld, _keep = _colmajor(Y, "Y")
-    h2 = _dev(h2, "h2", torch.float64).contiguous()
-    s2 = _dev(s2, "s2", torch.float64).contiguous()
+    sh = clak_plan_get_shape(plan)
+    ptr, ld, _keep = _colmajor(Y, "Y", (sh.n, sh.t))
+    h2 = _vector(h2, "h2", sh.t)
+    s2 = _vector(s2, "s2", sh.t)
     _check(lib().clak_set_traits(plan, ptr, ld, h2.data_ptr(), s2.data_ptr()), "clak_set_traits")
 
 
 def clak_estimate_vc(plan: int, Y: torch.Tensor, method: int = CLAK_VC_REML, h2: Optional[torch.Tensor] = None,
                      s2: Optional[torch.Tensor] = None, loglik: Optional[torch.Tensor] = None):
     """Per-trait (h2, s2, loglik) of the reduced model; outputs are allocated when not given (float64, t values)."""
-    ptr, ld, _keep = _colmajor(Y, "Y")
-    t = _keep.shape[1]  # must be the plan's t
+    sh = clak_plan_get_shape(plan)
+    ptr, ld, _keep = _colmajor(Y, "Y", (sh.n, sh.t))
+    t = sh.t
     outs = []
     for name, x in (("h2", h2), ("s2", s2), ("loglik", loglik)):
         if x is None:
             x = torch.empty(t, dtype=torch.float64, device=Y.device)
         x = _dev(x, name, torch.float64)
-        if not x.is_contiguous() or x.numel() < t:
-            raise ValueError(f"{name}: need a contiguous float64 tensor of at least t={t} values")
+        if x.dim() != 1 or not x.is_contiguous() or x.numel() != t:
+            raise ValueError(f"{name}: need a contiguous 1-D float64 tensor of t={t} values")
         outs.append(x)
     _check(lib().clak_estimate_vc(plan, ptr, ld, method, outs[0].data_ptr(), outs[1].data_ptr(), outs[2].data_ptr()),
            "clak_estimate_vc")
@@ -207,7 +252,7 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
                    g_dtype: Optional[int] = None):
     """G: (m_blk, ldg) uint8 or float16 SNP rows (uint8 rows of 2-bit codes with g_dtype=CLAK_G_P2);
     b, se, pval: (t, ldo[, p]) float32/64."""
-    blk, gdt, odt = _block_args(G, b, se, flags, pval, g_dtype)
+    blk, gdt, odt = _block_args(clak_plan_get_shape(plan), G, b, se, flags, pval, g_dtype)
     _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags,
                                 blk.pval), "clak_run_block")
 
@@ -216,35 +261,25 @@ def clak_bed_open(path: str, n: int, m: int, block: int, depth: int = 4) -> int:
     """Reader of a SNP-major PLINK 1 binary genotype file (n individuals, m SNPs) in blocks of `block` SNPs."""
     h = _P()
     _check(lib().clak_bed_open(ctypes.byref(h), os.fsencode(path), n, m, block, depth), "clak_bed_open")
+    _BED_SNPS[h.value] = int(m)
     return h.value
 
 
 def clak_bed_scan(bed: int, plan: int, b: torch.Tensor, se: torch.Tensor, flags: Optional[torch.Tensor] = None,
                   pval: Optional[torch.Tensor] = None):
     """Every SNP of the file through the plan; b, se, flags, pval: (t, ldo[, p]) with ldo >= m (synchronous)."""
-    for name, x in (("b", b), ("se", se)):
-        if not (isinstance(x, torch.Tensor) and x.is_cuda):
+    for name, x in (("b", b), ("se", se), ("flags", flags), ("pval", pval)):
+        if x is not None and not (isinstance(x, torch.Tensor) and x.is_cuda):
             raise ValueError(f"{name} must be a GPU tensor")
-    if b.dtype != se.dtype or b.dtype not in (torch.float32, torch.float64):
-        raise ValueError("b and se must share dtype float32 or float64")
-    if se.dim() != 2 or se.stride(1) != 1:
-        raise ValueError("se must be (t, ldo) with contiguous rows")
-    ldo = se.stride(0) if se.shape[0] > 1 else se.shape[1]
-    fptr = pptr = None
-    if flags is not None:
-        if flags.dtype != torch.uint8 or flags.shape != se.shape or flags.stride() != se.stride():
-            raise ValueError("flags must be uint8 with the layout of se")
-        fptr = flags.data_ptr()
-    if pval is not None:
-        if pval.dtype != se.dtype or pval.shape != se.shape or pval.stride() != se.stride():
-            raise ValueError("pval must match se")
-        pptr = pval.data_ptr()
-    odt = CLAK_OUT_F32 if b.dtype == torch.float32 else CLAK_OUT_F64
+    ldo, odt = _out_layout(clak_plan_get_shape(plan), b, se, flags, pval, _BED_SNPS.get(bed, 1))
+    fptr = flags.data_ptr() if flags is not None else None
+    pptr = pval.data_ptr() if pval is not None else None
     _check(lib().clak_bed_scan(bed, plan, b.data_ptr(), se.data_ptr(), odt, ldo, fptr, pptr), "clak_bed_scan")
 
 
 def clak_bed_close(bed: int):
     _check(lib().clak_bed_close(bed), "clak_bed_close")
+    _BED_SNPS.pop(bed, None)
 
 
 def clak_plan_set_tuning(plan: int, rot_cfg: int = 0, rot_rg: int = 0, grid_tt: int = 0, grid_xt: int = 0):
@@ -261,14 +296,16 @@ def clak_plan_get_tuning(plan: int):
 def clak_autotune(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
                   flags: Optional[torch.Tensor] = None, cache_path: Optional[str] = None):
     """clak_run_block that first picks (or reads from cache_path) the launch parameters."""
-    blk, gdt, odt = _block_args(G, b, se, flags)
+    blk, gdt, odt = _block_args(clak_plan_get_shape(plan), G, b, se, flags)
     cp = cache_path.encode() if cache_path is not None else None
     _check(lib().clak_autotune(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags, cp),
            "clak_autotune")
 
 
-def clak_plan_set_profiling(plan: int, enable: bool = True):
-    _check(lib().clak_plan_set_profiling(plan, 1 if enable else 0), "clak_plan_set_profiling")
+def clak_plan_set_profiling(plan: int, mode=CLAK_PROFILE_SERIAL):
+    """mode: CLAK_PROFILE_SERIAL (True), CLAK_PROFILE_PIPELINED, or CLAK_PROFILE_OFF (False)."""
+    mode = CLAK_PROFILE_SERIAL if mode is True else CLAK_PROFILE_OFF if mode is False else int(mode)
+    _check(lib().clak_plan_set_profiling(plan, mode), "clak_plan_set_profiling")
 
 
 def clak_plan_get_profile(plan: int):
@@ -279,48 +316,97 @@ def clak_plan_get_profile(plan: int):
     return {STAGE_NAMES[i]: (ms[i], n[i]) for i in range(CLAK_STAGE_COUNT)}
 
 
-def _block_args(G, b, se, flags=None, pval=None, g_dtype=None):
-    """(clak_block, g_dtype, out_dtype) for one block, with the checks of clak_run_block."""
-    _dev(G, "G")
-    if g_dtype == CLAK_G_P2:
-        if G.dtype != torch.uint8:
-            raise ValueError("2-bit genotype rows must be a uint8 tensor")
-        gdt = CLAK_G_P2
-    elif G.dtype == torch.uint8:
-        gdt = CLAK_G_U8
-    elif G.dtype == torch.float16:
-        gdt = CLAK_G_F16
-    else:
-        raise ValueError("G must be uint8 or float16")
-    if G.dim() != 2 or G.stride(1) != 1:
-        raise ValueError("G must be 2-D with contiguous rows (one SNP per row)")
-    _dev(b, "b")
-    _dev(se, "se")
+def clak_plan_get_busy(plan: int):
+    """{stage name: ms during which at least one of its timed launches ran} since profiling was enabled."""
+    busy = (ctypes.c_double * CLAK_STAGE_COUNT)()
+    _check(lib().clak_plan_get_busy(plan, ctypes.cast(busy, _P)), "clak_plan_get_busy")
+    return {STAGE_NAMES[i]: busy[i] for i in range(CLAK_STAGE_COUNT)}
+
+
+def _out_layout(shape: Shape, b, se, flags, pval, m_blk: int):
+    """(ldo, out_dtype) after checking the outputs of m_blk SNPs against the
+    plan: se (t, >= m_blk) with unit-strided rows, b with se's layout (or
+    (t, >= m_blk, p_L + 1), entries of a cell contiguous, under CLAK_OUT_FULL),
+    flags (uint8) and pval (se's dtype) with se's layout."""
+    t, p = shape.t, shape.p_L + 1
     if b.dtype != se.dtype or b.dtype not in (torch.float32, torch.float64):
         raise ValueError("b and se must share dtype float32 or float64")
     odt = CLAK_OUT_F32 if b.dtype == torch.float32 else CLAK_OUT_F64
     if se.dim() != 2 or se.stride(1) != 1:
         raise ValueError("se must be (t, ldo) with contiguous rows")
+    if se.shape[0] < t or se.shape[1] < m_blk:
+        raise ValueError(f"se has shape {tuple(se.shape)}; the plan writes (t={t}, m_blk={m_blk})")
     ldo = se.stride(0) if se.shape[0] > 1 else se.shape[1]
-    fptr = None
+    if ldo < se.shape[1]:
+        raise ValueError("se rows overlap (row stride below the row length)")
+
+    def same_rows(x, name, row_stride, trailing=()):
+        if x.dim() != 2 + len(trailing) or x.shape[0] < t or x.shape[1] < m_blk:
+            raise ValueError(f"{name} has shape {tuple(x.shape)}; the plan writes (t={t}, m_blk={m_blk}"
+                             + "".join(f", {d}" for d in trailing) + ")")
+        want = (row_stride,) + tuple(int(np.prod(trailing[i:])) for i in range(len(trailing) + 1))
+        got = tuple(x.stride())
+        if got[1:] != want[1:] or (t > 1 and got[0] != want[0]):
+            raise ValueError(f"{name} strides {got} do not match the output layout {want}")
+
+    if shape.flags & CLAK_OUT_FULL:
+        same_rows(b, "b", ldo * p, (p,))
+    else:
+        same_rows(b, "b", ldo)
     if flags is not None:
-        _dev(flags, "flags", torch.uint8)
-        if flags.shape != se.shape or flags.stride() != se.stride():
-            raise ValueError("flags must match the layout of se")
-        fptr = flags.data_ptr()
-    pptr = None
+        if flags.dtype != torch.uint8:
+            raise ValueError("flags must be uint8")
+        same_rows(flags, "flags", ldo)
     if pval is not None:
-        _dev(pval, "pval", se.dtype)
-        if pval.shape != se.shape or pval.stride() != se.stride():
-            raise ValueError("pval must match the layout of se")
-        pptr = pval.data_ptr()
-    blk = clak_block(G.shape[0], G.data_ptr(), G.stride(0), b.data_ptr(), se.data_ptr(), ldo, fptr, pptr)
+        if pval.dtype != se.dtype:
+            raise ValueError("pval must have the dtype of se")
+        same_rows(pval, "pval", ldo)
+    return ldo, odt
+
+
+def _block_layout(shape: Shape, G, b, se, flags=None, pval=None, g_dtype=None):
+    """(m_blk, ldg, g_dtype, ldo, out_dtype) of one block, every tensor checked
+    against the plan's sizes (device-independent part of the checks)."""
+    if g_dtype == CLAK_G_P2:
+        if G.dtype != torch.uint8:
+            raise ValueError("2-bit genotype rows must be a uint8 tensor")
+        gdt, row = CLAK_G_P2, (shape.n + 3) // 4
+    elif G.dtype == torch.uint8:
+        gdt, row = CLAK_G_U8, shape.n
+    elif G.dtype == torch.float16:
+        gdt, row = CLAK_G_F16, shape.n
+    else:
+        raise ValueError("G must be uint8 or float16")
+    if G.dim() != 2 or G.stride(1) != 1:
+        raise ValueError("G must be 2-D with contiguous rows (one SNP per row)")
+    m_blk = G.shape[0]
+    if not 1 <= m_blk <= shape.max_block:
+        raise ValueError(f"G holds {m_blk} SNPs; the plan takes 1 to max_block={shape.max_block}")
+    if G.shape[1] < row:
+        raise ValueError(f"G rows hold {G.shape[1]} entries; one SNP of n={shape.n} needs {row}")
+    ldg = G.stride(0) if m_blk > 1 else G.shape[1]
+    ldo, odt = _out_layout(shape, b, se, flags, pval, m_blk)
+    return m_blk, ldg, gdt, ldo, odt
+
+
+def _block_args(shape: Shape, G, b, se, flags=None, pval=None, g_dtype=None):
+    """(clak_block, g_dtype, out_dtype) for one block, with the checks of clak_run_block."""
+    _dev(G, "G")
+    _dev(b, "b")
+    _dev(se, "se")
+    if flags is not None:
+        _dev(flags, "flags")
+    if pval is not None:
+        _dev(pval, "pval")
+    m_blk, ldg, gdt, ldo, odt = _block_layout(shape, G, b, se, flags, pval, g_dtype)
+    blk = clak_block(m_blk, G.data_ptr(), ldg, b.data_ptr(), se.data_ptr(), ldo,
+                     flags.data_ptr() if flags is not None else None, pval.data_ptr() if pval is not None else None)
     return blk, gdt, odt
 
 
-def _block_array(blocks):
+def _block_array(shape: Shape, blocks):
     """blocks: sequence of (G, b, se[, flags[, pval]]) -> ctypes array, g_dtype, out_dtype."""
-    items = [_block_args(*blk) for blk in blocks]
+    items = [_block_args(shape, *blk) for blk in blocks]
     if not items:
         raise ValueError("no blocks")
     gdts = {it[1] for it in items}
@@ -334,7 +420,7 @@ def _block_array(blocks):
 def clak_pipeline_create(plan: int, blocks) -> int:
     """Two-stream pipeline over blocks = [(G, b, se[, flags]), ...]: the ingest of a block
     overlaps the rotation and grid of the previous one."""
-    arr, gdt, odt = _block_array(blocks)
+    arr, gdt, odt = _block_array(clak_plan_get_shape(plan), blocks)
     h = _P()
     _check(lib().clak_pipeline_create(ctypes.byref(h), plan, len(arr), arr, gdt, odt), "clak_pipeline_create")
     return h.value
@@ -350,8 +436,14 @@ def clak_pipeline_destroy(pipe: int):
 
 def clak_batch_create(plans, blocks_per_plan) -> int:
     """One submission over several plans (cohorts); blocks_per_plan[k] = [(G, b, se[, flags]), ...]."""
-    flat = [blk for bl in blocks_per_plan for blk in bl]
-    arr, gdt, odt = _block_array(flat)
+    if len(plans) != len(blocks_per_plan):
+        raise ValueError("one block list per plan")
+    parts = [_block_array(clak_plan_get_shape(p), bl) for p, bl in zip(plans, blocks_per_plan)]
+    if len({x[1] for x in parts}) != 1 or len({x[2] for x in parts}) != 1:
+        raise ValueError("all blocks must share the genotype and output dtypes")
+    flat = [blk for x in parts for blk in x[0]]
+    arr = (clak_block * len(flat))(*flat)
+    gdt, odt = parts[0][1], parts[0][2]
     ph = (_P * len(plans))(*plans)
     nb = (_I64 * len(plans))(*[len(bl) for bl in blocks_per_plan])
     h = _P()

@@ -82,10 +82,18 @@ def test_status_codes(w):
             assert e.value.status == clak.CLAK_E_ARG
         clak.clak_set_traits(h, Y, _t(np.array([0.5, 1.0])), _t(np.array([1.0, 2.0])))
         # block larger than max_block, bad leading dimension
-        with pytest.raises(ClakError) as e:
-            clak.clak_run_block(h, _t(w.genotypes(0, 17)), torch.empty((2, 17), dtype=torch.float64,
-                                device="cuda"), torch.empty((2, 17), dtype=torch.float64, device="cuda"))
-        assert e.value.status == clak.CLAK_E_ARG
+        G17 = _t(w.genotypes(0, 17))
+        b17 = torch.empty((2, 17), dtype=torch.float64, device="cuda")
+        se17 = torch.empty_like(b17)
+        with pytest.raises(ValueError):  # the binding checks against the plan's max_block first
+            clak.clak_run_block(h, G17, b17, se17)
+        # the library refuses the same call on its own
+        assert clak.lib().clak_run_block(h, 17, G17.data_ptr(), clak.CLAK_G_U8, w.n, b17.data_ptr(),
+                                         se17.data_ptr(), clak.CLAK_OUT_F64, 17, None, None) == clak.CLAK_E_ARG
+        assert clak.lib().clak_run_block(h, 16, G.data_ptr(), clak.CLAK_G_U8, w.n - 1, b.data_ptr(),
+                                         se.data_ptr(), clak.CLAK_OUT_F64, 16, None, None) == clak.CLAK_E_ARG
+        assert clak.lib().clak_run_block(h, 16, G.data_ptr(), clak.CLAK_G_U8, w.n, b.data_ptr(),
+                                         se.data_ptr(), clak.CLAK_OUT_F64, 15, None, None) == clak.CLAK_E_ARG
         clak.clak_run_block(h, G, b, se)
         torch.cuda.synchronize()
         assert torch.isfinite(b).all() and (se > 0).all()
