@@ -77,7 +77,7 @@ static int32_t solve_cell(int64_t n, int64_t p, const double* Xp, const double* 
       double s = S[i * p + j];
       for (int64_t k = 0; k < j; ++k) s -= Ls[i * p + k] * Ls[j * p + k];
       if (i == j) {
-        if (!(s > 1e-10 * S[j * p + j])) return j == p - 1 ? ORACLE_SNP_DEGENERATE : ORACLE_COV_SINGULAR;
+        if (!(s > ORACLE_DEGEN_TOL * S[j * p + j])) return j == p - 1 ? ORACLE_SNP_DEGENERATE : ORACLE_COV_SINGULAR;
         Ls[j * p + j] = sqrt(s);
       } else {
         Ls[i * p + j] = s / Ls[j * p + j];

@@ -23,9 +23,18 @@
 extern "C" {
 #endif
 
+/* Relative pivot test of chol(S): a pivot is degenerate when pivot^2 <=
+ * ORACLE_DEGEN_TOL * S_jj.  For the SNP's (last) pivot, pivot^2 / S_pp is the
+ * share of the SNP's M_j^{-1}-weighted squared norm left after projecting it
+ * on the covariates.  Overridable at compile time only so that a test can
+ * build a deliberately wrong oracle and check that the pins notice. */
+#ifndef ORACLE_DEGEN_TOL
+#define ORACLE_DEGEN_TOL 1e-10
+#endif
+
 /* Per-cell flags written by oracle_gls. */
 #define ORACLE_OK 0
-#define ORACLE_SNP_DEGENERATE 1   /* last pivot of chol(S): pivot^2 <= 1e-10 * S_pp */
+#define ORACLE_SNP_DEGENERATE 1   /* last pivot of chol(S): pivot^2 <= ORACLE_DEGEN_TOL * S_pp */
 #define ORACLE_M_NOT_SPD 2        /* chol(M_j) failed */
 #define ORACLE_COV_SINGULAR 3     /* a covariate pivot of chol(S) failed */
 

@@ -323,6 +323,73 @@ def test_degenerate_snps_flagged():
     assert np.isfinite(b[4]).all()
 
 
+def _near_collinear_snps(rho, seed=33, n=60):
+    """A problem and SNP columns g = X_L gamma + eps r, r orthogonal to X_L in
+    the M^{-1} inner product, with eps chosen so that the share of g's
+    M^{-1}-weighted squared norm outside span(X_L) is rho[k] for column k;
+    returns the problem and that share recomputed with numpy solves."""
+    rng = np.random.default_rng(seed)
+    Phi, XL, _, Y, h2, s2 = _rand_problem(rng, n, 3, t=1, ng=1)
+    M = s2[0] * (h2[0] * Phi + (1 - h2[0]) * np.eye(n))
+    Mi = lambda v: np.linalg.solve(M, v)
+    P = XL @ np.linalg.solve(XL.T @ Mi(XL), XL.T @ Mi(np.eye(n)))  # M^{-1}-orthogonal projector on X_L
+    base = XL @ np.array([1.3, -0.7, 0.02])
+    r = rng.normal(size=n)
+    r = r - P @ r
+    A, R = base @ Mi(base), r @ Mi(r)
+    G = np.stack([base + np.sqrt(q * A / (R * (1 - q))) * r for q in rho], 1)
+    share = np.array([(g - P @ g) @ Mi(g - P @ g) / (g @ Mi(g)) for g in G.T])
+    return Phi, XL, G, Y, h2, s2, share
+
+
+RHO_KEPT = [1e-8, 1e-9, 2e-10]    # above the degeneracy threshold 1e-10
+RHO_FLAGGED = [5e-11, 1e-12, 0.0]  # at or below it
+
+
+def _threshold_pin_holds():
+    """The oracle flags a cell exactly when the share of the SNP's
+    M^{-1}-weighted squared norm outside the covariates is <= 1e-10 (the
+    relative pivot test of reading R8), at shares a factor of two and more on
+    either side of the threshold; the kept cells match a numpy solve."""
+    rho = RHO_KEPT + RHO_FLAGGED
+    Phi, XL, G, Y, h2, s2, share = _near_collinear_snps(rho)
+    np.testing.assert_allclose(share[:len(RHO_KEPT)], RHO_KEPT, rtol=1e-3)
+    assert (share[len(RHO_KEPT):] <= 0.6e-10).all()
+    b, var, flag = oracle.gls_cells(Phi, XL, G, Y, h2, s2, np.arange(len(rho)), np.zeros(len(rho), int))
+    want = [oracle.OK] * len(RHO_KEPT) + [oracle.SNP_DEGENERATE] * len(RHO_FLAGGED)
+    if list(flag) != want:
+        return False
+    for c in range(len(RHO_KEPT)):
+        rb, rv = _gls_numpy(Phi, np.c_[XL, G[:, c]], Y[:, 0], h2[0], s2[0])
+        # conditioning grows like 1 / rho: relative accuracy ~1e-16 / rho
+        if not np.allclose(b[c, -1], rb[-1], rtol=1e-5) or not np.allclose(var[c, -1, -1], rv[-1, -1], rtol=1e-5):
+            return False
+    return bool(np.isnan(b[len(RHO_KEPT):]).all())
+
+
+def test_degeneracy_threshold():
+    assert _threshold_pin_holds()
+
+
+@pytest.mark.parametrize("tol", ["1e-3", "1e-14"])
+def test_degeneracy_threshold_pin_catches_a_wrong_constant(tmp_path, tol):
+    """A mutant oracle built with another pivot threshold fails the pin."""
+    import ctypes
+
+    from oracle.build import build
+    path = build(out=str(tmp_path / "liboracle_mutant.so"), defines=[f"ORACLE_DEGEN_TOL={tol}"])
+    good = oracle._lib()
+    mutant = ctypes.CDLL(path)
+    mutant.oracle_gls.argtypes = good.oracle_gls.argtypes
+    mutant.oracle_gls.restype = good.oracle_gls.restype
+    try:
+        oracle._LIB = mutant
+        assert not _threshold_pin_holds()
+    finally:
+        oracle._LIB = good
+    assert _threshold_pin_holds()
+
+
 def test_boundaries_and_not_spd():
     """h2 = 0 and h2 = 1 are valid for a positive-definite Phi; h2 = 1 with an
     indefinite Phi makes M_j indefinite, flagged per cell."""
