@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <string>
 #include <functional>
+#include <utility>
 #include <vector>
 
 #include "../../include/clak.h"
@@ -55,8 +56,6 @@ enum DevStatus : int {
   DS_COUNT = 64
 };
 
-// Buffers of one SNP block in flight.  The workspace holds two such slots so
-// that a pipeline can ingest block b+1 while block b is rotated.
 // Where the per-cell results of one block go: cell (i, j) at element
 // i + j * ldo (b holds p values per cell under CLAK_OUT_FULL).
 struct CellOut {
@@ -68,6 +67,8 @@ struct CellOut {
   int f64 = 0;  // element type of b, se and pval: double if set, else float
 };
 
+// Buffers of one SNP block in flight.  The workspace holds NSLOTS such slots
+// so that a pipeline can ingest blocks b+1 and b+2 while block b is rotated.
 struct Slot {
   int8_t* Gp = nullptr;
   double* sstat = nullptr;
@@ -152,16 +153,20 @@ struct Plan {
   // built-in choice): rotation tile configuration and XCD row groups, traits
   // per work-group and XCD trait groups of the grid contraction
   int rot_cfg = 0, rot_rg = 0, grid_tt = 0, grid_xt = 0;
-  // stage profiler: pending (stage, start, end) event triples and totals
-  bool profiling = false;
+  // stage profiler (CLAK_PROFILE_*): pending (stage, start, end) event
+  // triples, per-stage totals, and every launch's interval relative to the
+  // reference event recorded when profiling was enabled
+  int profiling = CLAK_PROFILE_OFF;
   struct Timed {
     int stage;
     hipEvent_t a, b;
   };
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
+  hipEvent_t prof_ref = nullptr;
   double stage_ms[CLAK_STAGE_COUNT] = {0, 0, 0, 0};
   int64_t stage_n[CLAK_STAGE_COUNT] = {0, 0, 0, 0};
+  std::vector<std::pair<double, double>> stage_iv[CLAK_STAGE_COUNT];
   int* hstat = nullptr;     // pinned host mirror of dstat
 };
 

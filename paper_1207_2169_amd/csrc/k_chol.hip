@@ -10,7 +10,7 @@
 // major upper-triangular U^-1 written by the triangular inversion is exactly
 // that array for U^-T once its strictly lower part (left over from H) and the
 // padding are cleared.
-#include "common.cuh"
+#include "common.hpp"
 
 namespace clak {
 

@@ -1,8 +1,8 @@
 // FP64 MFMA kernels: the rotations by Z^T (fixed operands X_L, Q_L, Y in both
 // precisions; the SNP blocks in the FP64 path) and the FP64 grid contraction
 // with its fused Schur-complement epilogue.
-#include "common.cuh"
-#include "schur.cuh"
+#include "common.hpp"
+#include "schur.hpp"
 
 namespace clak {
 

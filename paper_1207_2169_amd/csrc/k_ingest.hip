@@ -4,7 +4,7 @@
 // degeneracy flag).
 #include <hip/hip_fp16.h>
 
-#include "common.cuh"
+#include "common.hpp"
 
 namespace clak {
 

@@ -7,8 +7,8 @@
 // products exactly in int32, so the only rounding of the contractions is the
 // encoding of their operands (and, in the grid, the digit products of weight
 // 256^-4 and below, which are dropped).
-#include "common.cuh"
-#include "schur.cuh"
+#include "common.hpp"
+#include "schur.hpp"
 
 #include <type_traits>
 

@@ -3,7 +3,7 @@
 // planes of Z^T, the orthonormal basis of X_L, and the per-trait quantities of
 // the loop over traits in the multi-trait CLAK-Eig listing (D, S_TL, b_T and
 // the operand of the grid contraction).
-#include "common.cuh"
+#include "common.hpp"
 
 namespace clak {
 

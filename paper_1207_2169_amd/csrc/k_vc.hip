@@ -12,7 +12,7 @@
 // section search on the bracket around the best of them (ties to the smaller
 // h2) down to a width of 1e-7, keeping the better of its midpoint and the
 // best grid point.  One work-group per trait, FP64 throughout.
-#include "common.cuh"
+#include "common.hpp"
 
 namespace clak {
 

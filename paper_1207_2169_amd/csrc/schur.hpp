@@ -11,7 +11,7 @@
 //   z = b_snp / SE, p = erfc(|z| / sqrt 2)     (optional)
 #pragma once
 
-#include "common.cuh"
+#include "common.hpp"
 
 namespace clak {
 

@@ -6,6 +6,8 @@ eps_SE = max |SE - SE_ref| / SE_ref <= 1e-6.  A CPU emulation of this
 encoding (four digit planes of Z^T, four of x and of the operand, products
 of weight >= 256^-4 dropped) predicts ~4e-9 at n = 1000."""
 import numpy as np
+
+import oracle
 import pytest
 
 from synth import make_workload
@@ -77,10 +79,14 @@ def test_mixed_full_vector_and_paper_variance(cfg, kw):
     b, se, fl = gpu_run(w, clak.CLAK_PREC_MIXED, flags=flags, block=w.m, g_dtype="f16")
     ii, jj = _all_cells(w.m, w.t)
     rb, rse, rfl = oracle_cells(w, ii, jj, var_paper=True)
+    # each covariate effect in units of its own standard error (the diagonal of
+    # the oracle's model-consistent Var(b) = (X^T M^-1 X)^-1)
+    G = np.concatenate([w.genotypes(int(s), 1) for s in range(w.m)]).T.astype(np.float64)
+    _, var, _ = oracle.gls_cells(w.Phi, w.XL, G, w.Y, w.h2, w.s2, ii, jj)
+    se_cov = np.sqrt(np.diagonal(var, axis1=1, axis2=2)[:, :-1])
     bf = b.reshape(-1, w.pL + 1)
-    se_full = np.sqrt(np.array([1.0]))  # placeholder to keep shapes explicit
-    # covariate effects: compare in units of the largest SE of the cell's vector
+    eb_cov = float(np.max(np.abs(bf[:, :-1] - rb[:, :-1]) / se_cov))
+    print(f"eps_b snp={np.max(np.abs(bf[:, -1] - rb[:, -1]) / rse):.3e} covariates={eb_cov:.3e}", flush=True)
     assert np.max(np.abs(bf[:, -1] - rb[:, -1]) / rse) < TOL
     assert np.max(np.abs(se.ravel() - rse) / rse) < TOL
-    assert np.max(np.abs(bf[:, :-1] - rb[:, :-1]) / (np.abs(rb[:, :-1]) + 1.0)) < 1e-5
-    del se_full
+    assert eb_cov < TOL
