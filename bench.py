@@ -33,6 +33,7 @@ WORKLOADS = {
 }
 C3_BLOCK = 10_000
 PEAK = {"mixed": (5000.0, "int8 dense MFMA, 5.0 POP/s"), "fp64": (78.6, "FP64 dense MFMA, 78.6 TFLOP/s")}
+GRID_PRODUCTS = 10  # int8 digit products the grid kernel issues per algorithmic product
 
 
 def parse():
@@ -47,6 +48,8 @@ def parse():
     ap.add_argument("--eager", action="store_true",
                     help="call clak_run_block per block on one stream instead of the block pipeline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c2", action="store_true",
+                    help="skip the multi-trait sub-record (n=1000, p=4, m=1e5, t=1000) of the default run")
     ap.add_argument("--host-genotypes", action="store_true",
                     help="keep the genotypes in pinned host memory: the ingest kernel reads them over PCIe "
                          "(end-to-end rate with the host link; not the HBM-resident headline)")
@@ -144,10 +147,13 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=Non
     The step time comes from HIP events around `steps` passes (pipeline
     launches unless eager).  The per-stage times come from the library's stage
     profiler, which brackets every stage's kernel with HIP events on the
-    stream that kernel runs on; it is switched on for the timed region (its
-    events add a few microseconds between launches, so the step time is
-    taken from a first timed region without it and the stage times from a
-    second, profiled one of the same length)."""
+    stream that kernel runs on (its events add a few microseconds between
+    launches, so the step time is taken from a first timed region without it):
+    a second region of the same length runs the pipeline as the first did
+    (CLAK_PROFILE_PIPELINED: per stage the mean launch duration as the
+    pipeline overlaps it, and the busy time, the union of its launches'
+    intervals, which never exceeds the step), a third, shorter one runs every
+    kernel alone (CLAK_PROFILE_SERIAL: isolated launch durations)."""
     run = Pass(clak, plan, G, b, se, block, eager, pv)
     try:
         for _ in range(warmup):
@@ -161,14 +167,25 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=Non
         ev1.record()
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
-        clak.clak_plan_set_profiling(plan.handle, True)
+        clak.clak_plan_set_profiling(plan.handle, clak.CLAK_PROFILE_PIPELINED)
         for _ in range(steps):
             run()
-        prof = clak.clak_plan_get_profile(plan.handle)
-        clak.clak_plan_set_profiling(plan.handle, False)
-        prof = {k: (v[0] / steps, v[1] / steps) for k, v in prof.items()}
+        pipe = clak.clak_plan_get_profile(plan.handle)
+        busy = clak.clak_plan_get_busy(plan.handle)
+        serial_steps = max(1, min(steps, 3))
+        clak.clak_plan_set_profiling(plan.handle, clak.CLAK_PROFILE_SERIAL)
+        for _ in range(serial_steps):
+            run()
+        alone = clak.clak_plan_get_profile(plan.handle)
+        clak.clak_plan_set_profiling(plan.handle, clak.CLAK_PROFILE_OFF)
     finally:
         run.close()
+    prof = {}
+    for k, (tot, n) in pipe.items():
+        prof[k] = {"launches_per_step": n / steps,
+                   "mean_launch_ms": tot / n if n else 0.0,        # in the pipeline (overlapped)
+                   "busy_ms_per_step": busy[k] / steps,            # union of the launch intervals
+                   "isolated_launch_ms": alone[k][0] / alone[k][1] if alone[k][1] else 0.0}
     return ms, prof
 
 
@@ -210,6 +227,62 @@ def stage_flops(stage, w, block):
     if stage == "grid":
         return 2.0 * w.n * block * w.t * (w.pL + 2)
     return None
+
+
+def roofline(prof, w, block, precision, workload, tuning):
+    """Roofline of the stage that keeps the GPU busiest per step.
+
+    achieved = algorithmic flops of one launch x launches per step / the
+    stage's busy time per step (the union of its launch intervals in the
+    pipelined profiled pass: the time during which at least one of its
+    kernels ran, so at most the step), i.e. flops per launch / busy time per
+    launch.  Beside it: the mean launch duration in the pipeline (what a
+    rocprofv3 kernel trace of the same passes averages) and the isolated one."""
+    dom = max((k for k in prof if prof[k]["launches_per_step"] > 0), key=lambda k: prof[k]["busy_ms_per_step"])
+    d = prof[dom]
+    flops = stage_flops(dom, w, block)
+    if flops is None:
+        return None
+    peak, peak_name = PEAK[precision]
+    per_launch = d["busy_ms_per_step"] / d["launches_per_step"]
+    achieved = flops / (per_launch * 1e-3) / 1e12
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": committed_traffic(dom, precision, workload, tuning),
+            "kernel": KERNELS.get((dom, precision), (dom,))[0], "avg_launch_ms": per_launch,
+            "launches_per_step": d["launches_per_step"],
+            "basis": "in-pipeline busy time: union of the kernel's launch intervals (HIP events on each launch's "
+                     "own stream) per step / launches per step",
+            "mean_launch_ms_in_pipeline": d["mean_launch_ms"], "isolated_launch_ms": d["isolated_launch_ms"],
+            "frac_isolated": flops / (d["isolated_launch_ms"] * 1e-3) / 1e12 / peak if d["isolated_launch_ms"] else None,
+            "peak_source": peak_name}
+    if precision == "mixed" and dom == "rotate":
+        roof["issued_int8_ops_frac"] = 4 * achieved / peak  # four digit planes of Z^T per product
+    if precision == "mixed" and dom == "grid":
+        roof["issued_int8_ops_frac"] = GRID_PRODUCTS * achieved / peak  # digit products per algorithmic product
+    return roof
+
+
+def parity_sample(w, b_gpu, se_gpu, n_traits=20, n_snps=500, seed=8):
+    """eps_b, eps_SE of the GPU outputs against the oracle on n_traits random
+    traits x n_snps random SNPs of the workload (every pair), with the oracle's
+    time on the host."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    traits = np.sort(rng.choice(w.t, min(n_traits, w.t), replace=False))
+    snps = np.sort(rng.choice(w.m, min(n_snps, w.m), replace=False))
+    ii, jj = np.meshgrid(np.arange(snps.size), traits, indexing="ij")
+    G = np.concatenate([w.genotypes(int(s), 1) for s in snps]).T.astype(np.float64)
+    t0 = time.perf_counter()
+    rb, rv, rf = oracle.gls_cells(w.Phi, w.XL, G, w.Y, w.h2, w.s2, ii.ravel(), jj.ravel())
+    dt = time.perf_counter() - t0
+    rse = np.sqrt(rv[:, -1, -1])
+    gb = b_gpu[jj.ravel(), snps[ii.ravel()]].astype(np.float64)
+    gse = se_gpu[jj.ravel(), snps[ii.ravel()]].astype(np.float64)
+    ok = rf == 0
+    return {"eps_b": float(np.max(np.abs(gb[ok] - rb[ok, -1]) / rse[ok])),
+            "eps_se": float(np.max(np.abs(gse[ok] - rse[ok]) / rse[ok])), "cells_checked": int(ok.sum()),
+            "sample": f"{traits.size} random traits x {snps.size} random SNPs", "oracle_s": dt,
+            "oracle_threads": oracle.threads()}
 
 
 def cpu_baseline(w, b_gpu, se_gpu, target_s):
@@ -293,22 +366,7 @@ def main():
     ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager, pv)
     cells = m * w.t
     log(f"[bench] {ms:.3f} ms/step, {cells / ms * 1e3:.4e} cells/s; stages {prof}")
-
-    # dominant kernel and its roofline (algorithmic flops / average launch duration)
-    dom = max((k for k in prof if prof[k][1] > 0), key=lambda k: prof[k][0])
-    avg_ms = prof[dom][0] / prof[dom][1]
-    flops = stage_flops(dom, w, block)
-    peak, peak_name = PEAK[args.precision]
-    roof = None
-    if flops is not None:
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": committed_traffic(dom, args.precision, args.workload, tuning), "kernel": KERNELS.get(
-                    (dom, args.precision), (dom,))[0], "avg_launch_ms": avg_ms, "launches_per_step": prof[dom][1],
-                "peak_source": peak_name}
-        if args.precision == "mixed" and dom == "rotate":
-            roof["issued_int8_ops_frac"] = 4 * achieved / peak  # four digit planes of Z^T per product
-
+    roof = roofline(prof, w, block, args.precision, args.workload, tuning)
     out = {
         "metric": "GLS cells/sec (SNP x trait) at n=1000, p=4; mixed precision vs FP64",
         "value": cells / (ms * 1e-3),
@@ -327,7 +385,7 @@ def main():
                    "precision": args.precision, "parallelism": "single GPU", "tuning": tuning,
                    "outputs": "b, SE, p-value" if args.pval else "b, SE"},
         "roofline": roof,
-        "stage_ms_per_step": {k: v[0] for k, v in prof.items()},
+        "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in prof.items()},
         "launch": "per-block clak_run_block calls, one stream" if args.eager else
                   "clak_pipeline_launch: ingest on a side stream overlapped with rotation",
         "setup_ms": setup,
@@ -343,7 +401,8 @@ def main():
                                    pv)
         p64.close()
         out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
-                             "stage_ms_per_step": {k: v[0] for k, v in prof64.items()}}
+                             "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in prof64.items()},
+                             "roofline": roofline(prof64, w, block, "fp64", args.workload, None)}
         out["mixed_over_fp64"] = ms64 / ms
         log(f"[bench] FP64 plain path: {ms64:.3f} ms/step")
 
@@ -359,7 +418,7 @@ def main():
         pc.close()
         zc = (bc.double() - b.double()).abs() / se.double()
         out["clak_chol"] = {"value": cells / (msc * 1e-3), "ms_per_step": msc,
-                            "stage_ms_per_step": {k: v[0] for k, v in profc.items()},
+                            "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in profc.items()},
                             "setup_ms": {k: v for k, v in setup_c.items() if k != "vc_reml_ms"},
                             "max_abs_diff_vs_eig_in_se_units": float(zc.max().item())}
         log(f"[bench] CLAK-Chol: {msc:.3f} ms/step, max |b_chol - b_eig| / SE = {zc.max().item():.3e}")
@@ -409,7 +468,46 @@ def main():
         cb, err = cpu_baseline(w, b_h, se_h, args.cpu_seconds)
         out["cpu_baseline"] = cb
         out["parity_sample"] = err
+    if args.workload == "c1" and not args.no_c2 and args.m is None:
+        del G, b, se, pv
+        torch.cuda.empty_cache()
+        out["c2"] = multi_trait_record(args, clak, torch)
     print(json.dumps(out), flush=True)
+
+
+def multi_trait_record(args, clak, torch):
+    """The multi-trait workload (n=1000, p=4, m=1e5 in blocks of 1e4,
+    t=1000: the configuration the metric is quoted on for many traits) timed
+    like the headline: its rate, its dominant kernel's roofline, and the
+    oracle's agreement on 20 random traits x 500 random SNPs."""
+    from synth import make_workload
+    cfg, wname = WORKLOADS["c2"]
+    log(f"[bench] multi-trait sub-record: {wname}")
+    w = make_workload(cfg)
+    G = upload_genotypes(w, w.m, torch)
+    b = torch.empty((w.t, w.m), dtype=torch.float32, device="cuda")
+    se = torch.empty_like(b)
+    plan, setup = make_plan(clak, torch, w, w.block, args.precision)
+    tuning = None
+    if not args.no_tune:
+        clak.clak_autotune(plan.handle, G[:w.block], b[:, :w.block], se[:, :w.block], cache_path=args.tune_cache)
+        tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
+    ms, prof = timed_steps(clak, torch, plan, G, b, se, w.block, args.steps, args.warmup, args.eager)
+    plan.close()
+    cells = w.m * w.t
+    log(f"[bench] multi-trait: {ms:.3f} ms/step, {cells / ms * 1e3:.4e} cells/s")
+    rec = {"workload": wname, "value": cells / (ms * 1e-3), "unit": "cells/s", "ms_per_step": ms,
+           "steps": args.steps, "warmup": args.warmup, "dtype": "i8" if args.precision == "mixed" else "f64",
+           "config": {"n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": w.m, "t": w.t, "block": w.block,
+                      "precision": args.precision, "tuning": tuning},
+           "roofline": roofline(prof, w, w.block, args.precision, "c2", tuning),
+           "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in prof.items()},
+           "setup_ms": setup}
+    rec["parity_sample"] = parity_sample(w, b.cpu().numpy(), se.cpu().numpy())
+    log(f"[bench] multi-trait parity {rec['parity_sample']}")
+    del G, b, se
+    torch.cuda.empty_cache()
+    return rec
 
 
 def run_cohorts(args, clak, torch):
@@ -450,12 +548,13 @@ def run_cohorts(args, clak, torch):
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / args.steps
         for h in handles:
-            clak.clak_plan_set_profiling(h, True)
+            clak.clak_plan_set_profiling(h, clak.CLAK_PROFILE_PIPELINED)
         for _ in range(args.steps):
             clak.clak_batch_launch(batch)
         profs = [clak.clak_plan_get_profile(h) for h in handles]
+        busys = [clak.clak_plan_get_busy(h) for h in handles]
         for h in handles:
-            clak.clak_plan_set_profiling(h, False)
+            clak.clak_plan_set_profiling(h, clak.CLAK_PROFILE_OFF)
     finally:
         clak.clak_batch_destroy(batch)
     cells = sum(w.m * w.t for w in ws)
@@ -478,7 +577,8 @@ def run_cohorts(args, clak, torch):
                      "frac": achieved / peak, "traffic": None, "kernel": "k_rot_i8 + k_grid32 (all cohorts)",
                      "basis": "rotation and grid flops of all cohorts per step / wall time of the step",
                      "peak_source": peak_name},
-        "stage_ms_summed_over_cohorts": {k: sum(p[k][0] for p in profs) / args.steps for k in profs[0]},
+        "stage_launch_ms_summed_over_cohorts": {k: sum(p[k][0] for p in profs) / args.steps for k in profs[0]},
+        "stage_busy_ms_per_cohort": [{k: v / args.steps for k, v in bz.items()} for bz in busys],
         "launch": "clak_batch_launch: one pipeline per cohort on its own streams, cohorts concurrent",
         "setup_ms": setup,
     }

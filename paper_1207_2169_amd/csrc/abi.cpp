@@ -3,6 +3,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -95,20 +96,42 @@ hipEvent_t take_event(Plan* p) {
   return e;
 }
 
-// Waits for every timed stage, adds its duration, recycles the events.
+// Waits for every timed stage, adds its duration, keeps its interval
+// relative to the reference event, recycles the events.
 clak_status drain_profile(Plan* p) {
   if (p->pending.empty()) return CLAK_OK;
-  HIP_TRY(hipStreamSynchronize(p->stream));
+  HIP_TRY(hipDeviceSynchronize());  // the bracketing events may sit on any stream of a pipeline
   for (auto& t : p->pending) {
-    float ms = 0.0f;
+    float ms = 0.0f, a = 0.0f, b = 0.0f;
     HIP_TRY(hipEventElapsedTime(&ms, t.a, t.b));
+    HIP_TRY(hipEventElapsedTime(&a, p->prof_ref, t.a));
+    HIP_TRY(hipEventElapsedTime(&b, p->prof_ref, t.b));
     p->stage_ms[t.stage] += ms;
     p->stage_n[t.stage] += 1;
+    p->stage_iv[t.stage].push_back({(double)a, (double)b});
     p->event_pool.push_back(t.a);
     p->event_pool.push_back(t.b);
   }
   p->pending.clear();
   return CLAK_OK;
+}
+
+// Length of the union of a stage's launch intervals (the time during which at
+// least one of its kernels ran).
+static double busy_ms(std::vector<std::pair<double, double>> iv) {
+  std::sort(iv.begin(), iv.end());
+  double total = 0.0, s = 0.0, e = -1e300;
+  for (auto& x : iv) {
+    if (x.first > e) {
+      if (e > s) total += e - s;
+      s = x.first;
+      e = x.second;
+    } else if (x.second > e) {
+      e = x.second;
+    }
+  }
+  if (!iv.empty() && e > s) total += e - s;
+  return total;
 }
 
 clak_status sync_and_read_status(Plan* p) {
@@ -601,6 +624,19 @@ clak_status clak_plan_set_tuning(clak_plan_t h, int rot_cfg, int rot_rg, int gri
   return ok();
 }
 
+clak_status clak_plan_get_shape(clak_plan_t h, int64_t* n, int64_t* p_L, int64_t* t, int64_t* max_block,
+                                int* precision, uint32_t* flags) {
+  Plan* p = as_plan(h);
+  if (!p) return fail(CLAK_E_ARG, "plan_get_shape: null plan");
+  if (n) *n = p->n;
+  if (p_L) *p_L = p->pL;
+  if (t) *t = p->t;
+  if (max_block) *max_block = p->max_block;
+  if (precision) *precision = p->prec;
+  if (flags) *flags = p->flags;
+  return ok();
+}
+
 clak_status clak_plan_get_tuning(clak_plan_t h, int* rot_cfg, int* rot_rg, int* grid_tt, int* grid_xt) {
   Plan* p = as_plan(h);
   if (!p) return fail(CLAK_E_ARG, "plan_get_tuning: null plan");
@@ -658,8 +694,8 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
     if (e0) (void)hipEventDestroy(e0);
     return fail(CLAK_E_DEVICE, "autotune: event creation failed");
   }
-  const bool prof = p->profiling;
-  p->profiling = false;
+  const int prof = p->profiling;
+  p->profiling = CLAK_PROFILE_OFF;
   hipError_t err = hipSuccess;
   auto time_ms = [&](auto&& launch) -> float {
     float best = 1e30f;
@@ -727,16 +763,24 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   return s ? s : ok();
 }
 
-clak_status clak_plan_set_profiling(clak_plan_t h, int enable) {
+clak_status clak_plan_set_profiling(clak_plan_t h, int mode) {
   Plan* p = as_plan(h);
   if (!p) return fail(CLAK_E_ARG, "plan_set_profiling: null plan");
+  if (mode != CLAK_PROFILE_OFF && mode != CLAK_PROFILE_SERIAL && mode != CLAK_PROFILE_PIPELINED)
+    return fail(CLAK_E_ARG, "plan_set_profiling: unknown mode %d", mode);
   clak_status s = drain_profile(p);
   if (s) return s;
   for (int i = 0; i < CLAK_STAGE_COUNT; ++i) {
     p->stage_ms[i] = 0.0;
     p->stage_n[i] = 0;
+    p->stage_iv[i].clear();
   }
-  p->profiling = enable != 0;
+  if (mode != CLAK_PROFILE_OFF) {
+    if (!p->prof_ref && hipEventCreate(&p->prof_ref) != hipSuccess)
+      return fail(CLAK_E_DEVICE, "plan_set_profiling: event creation failed");
+    HIP_TRY(hipEventRecord(p->prof_ref, p->stream));
+  }
+  p->profiling = mode;
   return ok();
 }
 
@@ -752,6 +796,15 @@ clak_status clak_plan_get_profile(clak_plan_t h, double* ms, int64_t* launches) 
   return ok();
 }
 
+clak_status clak_plan_get_busy(clak_plan_t h, double* busy) {
+  Plan* p = as_plan(h);
+  if (!p || !busy) return fail(CLAK_E_ARG, "plan_get_busy: null argument");
+  clak_status s = drain_profile(p);
+  if (s) return s;
+  for (int i = 0; i < CLAK_STAGE_COUNT; ++i) busy[i] = busy_ms(p->stage_iv[i]);
+  return ok();
+}
+
 clak_status clak_plan_destroy(clak_plan_t h) {
   Plan* p = as_plan(h);
   if (!p) return fail(CLAK_E_ARG, "plan_destroy: null plan");
@@ -761,6 +814,7 @@ clak_status clak_plan_destroy(clak_plan_t h) {
     p->event_pool.push_back(t.b);
   }
   for (hipEvent_t e : p->event_pool) (void)hipEventDestroy(e);
+  if (p->prof_ref) (void)hipEventDestroy(p->prof_ref);
   if (p->rocblas) rocblas_destroy_handle((rocblas_handle)p->rocblas);
   if (p->hstat) (void)hipHostFree(p->hstat);
   delete p;

@@ -66,11 +66,11 @@ void release(Schedule* g) {
   delete g;
 }
 
-// The compute stream of block j.  While the stage profiler runs, every block
-// uses one, so that each kernel's bracketed time is its own (consecutive
-// blocks do not overlap).
+// The compute stream of block j.  While the serial stage profiler runs,
+// every block uses one, so that each kernel's bracketed time is its own
+// (consecutive blocks do not overlap).
 hipStream_t compute_stream(const Plan* p, const PlanStreams& c, int64_t j) {
-  return p->profiling ? c.s_main[0] : c.s_main[j % NCOMPUTE];
+  return p->profiling == CLAK_PROFILE_SERIAL ? c.s_main[0] : c.s_main[j % NCOMPUTE];
 }
 
 #define CK(expr, what)                                                                      \
@@ -111,15 +111,15 @@ clak_status run_schedule(Schedule* g, hipStream_t origin, const char* what) {
   for (auto& c : g->ps) {
     Plan* p = c.plan;
     // compute streams this launch uses (one for a single block or while profiling)
-    const int nmain = (p->profiling || c.count < 2) ? 1 : NCOMPUTE;
+    const int nmain = (p->profiling == CLAK_PROFILE_SERIAL || c.count < 2) ? 1 : NCOMPUTE;
     for (int q = 0; q < nmain; ++q) CK(hipStreamWaitEvent(c.s_main[q], g->fork, 0), what);
     CK(hipStreamWaitEvent(c.s_in, g->fork, 0), what);
     for (int64_t j = 0; j < c.count; ++j) {
       const int slot = (int)(j % NSLOTS);
       const hipStream_t sm = compute_stream(p, c, j);
-      // while profiling the ingest runs on the compute stream too, so that
-      // every stage is timed without a concurrent kernel
-      const hipStream_t si = p->profiling ? sm : c.s_in;
+      // while profiling serially the ingest runs on the compute stream too, so
+      // that every stage is timed without a concurrent kernel
+      const hipStream_t si = p->profiling == CLAK_PROFILE_SERIAL ? sm : c.s_in;
       if (j >= NSLOTS) CK(hipStreamWaitEvent(si, c.done[slot], 0), what);
       const clak_block& B = g->blocks[c.first + j];
       clak_status st = enqueue_block(p, slot, si, sm, c.ingested[slot], B.m_blk, B.G, g->g_dtype,
@@ -182,7 +182,7 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
     if ((result = get(j, &B))) break;
     if ((result = validate_block(p, B.m_blk, B.G, g_dtype, B.ldg, B.b, B.se, out_dtype, B.ldo, B.flags, B.pval))) break;
     const hipStream_t sm = compute_stream(p, c, j);
-    const hipStream_t si = p->profiling ? sm : c.s_in;  // as in run_schedule
+    const hipStream_t si = p->profiling == CLAK_PROFILE_SERIAL ? sm : c.s_in;  // as in run_schedule
     if (j >= NSLOTS && (result = ck(hipStreamWaitEvent(si, c.done[slot], 0)))) break;
     if ((result = enqueue_block(p, slot, si, sm, c.ingested[slot], B.m_blk, B.G, g_dtype, B.ldg,
                                 cell_out(B.b, B.se, B.pval, B.flags, B.ldo, out_dtype))))
