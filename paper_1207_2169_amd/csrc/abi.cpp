@@ -140,6 +140,29 @@ clak_status sync_and_read_status(Plan* p) {
   return CLAK_OK;
 }
 
+// Carves the buffers of one block slot from base (256-byte aligned pieces);
+// returns their size.  With base == nullptr only the size is computed.
+size_t slot_bytes(const Plan& p, Slot* S, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return ptr;
+  };
+  const size_t np = p.n_pad, pl = p.pL, mb = p.mb_pad;
+  Slot tmp;
+  Slot& T = S ? *S : tmp;
+  T = Slot();
+  T.Gp = (int8_t*)take(mb * np);
+  T.sstat = (double*)take(8 * mb * snp_stride(p.pL));
+  T.ipart = (double*)take(8 * ING_MAX_SPLITS * (pl + 2) * mb);
+  if (p.fused_t1) T.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
+  if (!p.fused_t1) T.X64 = (double*)take(8 * mb * np);
+  if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) T.Xd = (int8_t*)take(8 * mb * np);
+  if (p.flags & CLAK_STAGE_GENOTYPES) T.Gh = (uint8_t*)take(p.max_block * host_pitch(p.n));
+  return off;
+}
+
 // Carves the workspace.  With base == nullptr only the size is computed.
 size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   size_t off = 0;
@@ -148,7 +171,7 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
     off += (bytes + 255) / 256 * 256;
     return ptr;
   };
-  const size_t np = p.n_pad, pl = p.pL, tp = p.t_pad, mb = p.mb_pad;
+  const size_t np = p.n_pad, pl = p.pL, tp = p.t_pad;
   Workspace tmp;
   Workspace& W = w ? *w : tmp;
   W.Zt = (double*)take(8 * p.zrows * np);
@@ -182,14 +205,8 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
     W.ds = (double*)take(8 * tp);
   }
   for (int k = 0; k < NSLOTS; ++k) {
-    Slot& S = W.slot[k];
-    S.Gp = (int8_t*)take(mb * np);
-    S.sstat = (double*)take(8 * mb * snp_stride(p.pL));
-    S.ipart = (double*)take(8 * ING_MAX_SPLITS * (pl + 2) * mb);
-    if (p.fused_t1) S.part = (double*)take(8 * (np / 64) * mb * (pl + 2));
-    if (!p.fused_t1) S.X64 = (double*)take(8 * mb * np);
-    if (p.prec == CLAK_PREC_MIXED && !p.fused_t1) S.Xd = (int8_t*)take(8 * mb * np);
-    if (p.flags & CLAK_STAGE_GENOTYPES) S.Gh = (uint8_t*)take(p.max_block * host_pitch(p.n));
+    const size_t sb = slot_bytes(p, &W.slot[k], base ? base + off : nullptr);
+    off += sb;
   }
   if (w) {
     const Slot& S = W.slot[0];
@@ -326,7 +343,10 @@ static clak_status chol_factor(Plan* p, const double* d_h2) {
   HIP_TRY(launch_check_eigen(*p));
   if (p->prec == CLAK_PREC_MIXED) HIP_TRY(launch_split_digits(*p, 0, p->n_pad));
   HIP_TRY(launch_rotate_real(*p, W.XL, np, p->pL, W.XLt, np));
-  HIP_TRY(launch_rotate_real(*p, W.QL, np, p->pL, W.Qt, np));
+  if (p->prec == CLAK_PREC_MIXED)
+    HIP_TRY(launch_qt_digits(*p));  // the centring rotation by the digit-encoded operand
+  else
+    HIP_TRY(launch_rotate_real(*p, W.QL, np, p->pL, W.Qt, np));
   s = sync_and_read_status(p);
   if (s) return s;
   if (p->hstat[DS_EIG_INFO] != 0) return fail(CLAK_E_NOT_SPD, "set_traits: singular Cholesky factor");
@@ -424,7 +444,10 @@ clak_status clak_set_covariates(clak_plan_t h, const double* d_XL, int64_t ld) {
                              p->pL, hipMemcpyDeviceToDevice, p->stream));
   } else {
     HIP_TRY(launch_rotate_real(*p, d_XL, ld, p->pL, W.XLt, p->n_pad));
-    HIP_TRY(launch_rotate_real(*p, W.QL, p->n_pad, p->pL, W.Qt, p->n_pad));
+    if (p->prec == CLAK_PREC_MIXED)
+      HIP_TRY(launch_qt_digits(*p));  // the centring rotation by the digit-encoded Z^T
+    else
+      HIP_TRY(launch_rotate_real(*p, W.QL, p->n_pad, p->pL, W.Qt, p->n_pad));
   }
   s = sync_and_read_status(p);
   if (s) return s;
@@ -458,11 +481,7 @@ clak_status clak_set_traits(clak_plan_t h, const double* d_Y, int64_t ldy, const
   HIP_TRY(hipMemcpy2DAsync(W.tpar + p->pL * p->pL + p->pL + 1, sizeof(double) * ts, d_h2, sizeof(double),
                            sizeof(double), p->t, hipMemcpyDeviceToDevice, p->stream));
   HIP_TRY(launch_traits(*p));
-  if (lin_rows(*p)) {
-    // the extra rotation rows U^T = (Z W)^T and their digits
-    HIP_TRY(launch_uproj(*p));
-    HIP_TRY(launch_split_digits(*p, p->zlin, p->zrows));
-  }
+  if (lin_rows(*p)) HIP_TRY(launch_uproj(*p));  // the extra rotation rows U^T = (Z W)^T and their digits
   s = sync_and_read_status(p);
   if (s) return s;
   if (p->hstat[DS_TRAIT_ARG])

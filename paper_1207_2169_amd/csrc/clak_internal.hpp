@@ -171,6 +171,7 @@ struct Plan {
 };
 
 size_t workspace_bytes(const Plan& p, Workspace* carve, char* base);
+size_t slot_bytes(const Plan& p, Slot* carve, char* base);
 
 // Number of work-groups the ingest splits the individuals of one SNP group
 // over: one per 128-individual window, at most ING_MAX_SPLITS.  It depends on
@@ -225,9 +226,31 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
                           const std::function<clak_status(int64_t, clak_block*)>& get,
                           const std::function<clak_status(int64_t, hipStream_t)>& after, const char* what);
 
+// One plan's block in a batched launch (several plans' blocks in one grid):
+// the plan, the workspace slot the block uses, its size, input and outputs.
+struct BatchItem {
+  Plan* p = nullptr;
+  int slot = 0;
+  int64_t m_blk = 0;
+  const void* G = nullptr;
+  int64_t ldg = 0;
+  CellOut out;
+};
+
+// ---- batched launchers: one grid over every item, on stream s (plans that
+// batch_compatible accepts: mixed precision, several traits, the same p_L <= 3
+// and output form, no copy-engine staging) ----
+bool batch_compatible(const Plan& a, const Plan& b);
+hipError_t launch_ingest_batch(const BatchItem* items, int count, int g_dtype, hipStream_t s);
+hipError_t launch_rotate_batch(const BatchItem* items, int count, hipStream_t s);
+hipError_t launch_encode_batch(const BatchItem* items, int count, hipStream_t s);
+hipError_t launch_grid_batch(const BatchItem* items, int count, hipStream_t s);
+
 // ---- launchers (implemented in the .hip files; all enqueue on p.stream) ----
 // set-up
 hipError_t launch_split_digits(const Plan& p, int64_t r0, int64_t r1);
+hipError_t launch_dequant_rows(const Plan& p, int64_t r0, int64_t r1);
+hipError_t launch_qt_digits(const Plan& p);
 hipError_t launch_covariates(const Plan& p, const double* d_XL, int64_t ld);
 hipError_t launch_rotate_real(const Plan& p, const double* B, int64_t ldb, int64_t ncols, double* out,
                               int64_t ldo);
@@ -244,5 +267,6 @@ hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);
 hipError_t launch_encode(const Plan& p, int64_t m_blk);
 hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out);
 hipError_t launch_grid(const Plan& p, int64_t m_blk, const CellOut& out);
+hipError_t launch_grid_ring(const Plan& p, int64_t m_blk, const CellOut& out);
 
 }  // namespace clak

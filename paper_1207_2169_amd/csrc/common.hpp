@@ -88,4 +88,57 @@ __device__ __forceinline__ int quantize(double v, double inv_scale) {
   return (int)q;
 }
 
+// v_mfma_i32_32x32x32_i8 lane layout (gfx950): lane l supplies 16 bytes of row
+// l%32 of A and of column l%32 of B, the same 16 values of the 32-deep
+// contraction (half l/32); result register r holds C[8(r/4) + 4(l/32) + r%4][l%32].
+__device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
+}
+
+// Encoded s_waitcnt immediate that waits until at most N vector memory
+// operations of the wave are outstanding (expcnt and lgkmcnt not waited on).
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+// Work-group barrier for the direct-load ring: the wave's LDS reads complete
+// (lgkmcnt 0), then s_barrier.  Unlike __syncthreads it does not wait for
+// the wave's outstanding global-to-LDS loads; the caller waits for the ones
+// it needs (wait_vm) before the barrier.  The memory clobbers keep the
+// compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// Value of four digit-weight accumulators (weights 256^3 .. 1) at register
+// r, exact in FP64 (|sum| < 2^53 for the sizes the mixed path accepts).
+__device__ __forceinline__ double g32_value(const v16i (&acc)[4], int r) {
+  return (((double)acc[0][r] * 256.0 + (double)acc[1][r]) * 256.0 + (double)acc[2][r]) * 256.0 + (double)acc[3][r];
+}
+
+
+// Several plans' launches of one kernel as one grid: plan k takes work-groups
+// [start[k], start[k + 1]) of the flattened grid (its own grid, flattened,
+// after the plans before it; every range a multiple of 8 where the kernel's
+// tile map is XCD-aware, so that a work-group's XCD is its local index mod 8).
+constexpr int MAX_BATCH = 16;
+template <class A>
+struct BatchArgs {
+  int count;
+  int64_t start[MAX_BATCH + 1];
+  A a[MAX_BATCH];
+};
+
+// The plan that work-group b of a batched grid belongs to.
+template <class A>
+__device__ __forceinline__ int batch_plan(const BatchArgs<A>& B, int64_t b) {
+  int k = 0;
+  for (int q = 1; q < B.count; ++q) k += (b >= B.start[q]) ? 1 : 0;
+  return k;
+}
+
 }  // namespace clak

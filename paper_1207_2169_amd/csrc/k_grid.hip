@@ -1,0 +1,384 @@
+// Grid contraction of the multi-trait CLAK-Eig listing (section 3, the inner
+// loop over (SNP, trait) cells: W_R^T W_L, W_R^T Y_j and W_R^T W_R per cell)
+// in one pass over the individuals, on v_mfma_i32_32x32x32_i8.
+//
+// For a rotated, centred SNP x and trait j the cell needs p_L + 2 sums over
+// the n eigen indices k (the operand columns built by the trait kernel):
+//   c'_q = V_q^T x  (q < p_L, whitened covariates),  r' = (D e)^T x,
+//   a    = d^T (x o x).
+// Every operand is four int8 digit planes with one FP64 scale; a sum is the
+// ten digit products of total weight 256^-g, g <= 3, accumulated exactly in
+// four int32 accumulators (one per g).
+//
+// A work-group takes 128 SNPs x 32 traits with four waves, one per SIMD; wave
+// w owns the 32 x 32 cells of SNP rows 32 w .. 32 w + 31 and keeps every sum
+// of them in its accumulators: p_L + 2 MFMA tiles of 32 x 32, 64 registers
+// each (320 for p_L = 3, within the 512 registers of one wave per SIMD).
+// (p_L <= 3; larger p_L take the two-stage kernel of k_mixed.hip.)
+//
+// Staging: a ring of three 32-deep K slices in LDS, filled by direct
+// global-to-LDS loads (global_load_lds_dwordx4) of whole 1 KB MFMA fragments
+// (32 rows x 32 bytes of K, the kt32 layout of every digit plane), two slices
+// in flight while one is multiplied; no staging registers, no LDS stores by
+// the waves.  Wave w loads the x (and x o x) fragments of its own SNP rows and
+// plane w of every trait operand tile.
+//
+// Work-groups go round-robin over the 8 XCDs.  XCD x owns a contiguous range
+// of the block's SNP tiles and walks all trait groups for sg of them at a
+// time, so that the work-groups resident on one XCD share those SNP tiles'
+// digits and the trait groups' operand in its L2.
+//
+// Epilogue: per cell the Schur solve in FP64 (as schur_store), then each
+// wave stages its 32 x 32 results per output array in LDS and writes them
+// trait row by trait row, 32 consecutive SNPs per half-wave store.
+#include "common.hpp"
+#include "schur.hpp"
+
+namespace clak {
+
+// The tiles of a cell with p_L = PL <= 3: entries c'_0 .. c'_{p_L-1}, r'
+// (against x) and a (against x o x), p_L + 2 <= 5 tiles, 320 accumulator
+// registers at most.  (Larger p_L would need several passes over K; the
+// two-stage kernel of k_mixed.hip serves them.)
+template <int PL>
+struct GridTiles {
+  static constexpr int NT = PL + 2;
+  // fragments per slice: x planes of the 4 SNP row tiles, x o x planes, then
+  // 4 planes of each trait operand tile
+  static constexpr int FA = 32;
+  static constexpr int FB = 4 * NT;
+  static constexpr int FS = FA + FB;
+  static constexpr int LPW = FS / 4;  // direct loads per wave per slice
+  static_assert(PL >= 1 && PL <= 3, "one pass holds p_L <= 3");
+};
+
+constexpr int GR_SLOT = 52 * 1024;  // largest slice: 16 + 16 + 4 x 5 fragments
+constexpr int GR_STAGE = 32 * 33;   // per-wave epilogue staging: 32 traits x (32 SNPs + 1)
+
+// Arguments of the grid contraction of one plan's block (see grid_tile).
+struct GridArgs {
+  int64_t np, m_blk, mbp, t, tp, ns, ng;
+  int sg;
+  const int8_t* Xd;
+  const int8_t* Vd;
+  const int8_t* Dd;
+  const double* vs;
+  const double* ds;
+  const double* tpar;
+  const double* sstat;
+  uint32_t flags;
+  CellOut out;
+};
+
+// Work-group bid of the grid of one plan's block.
+template <int PL, bool FULL>
+__device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
+  const int64_t np = ga.np, m_blk = ga.m_blk, mbp = ga.mbp, t = ga.t, tp = ga.tp, ns = ga.ns, ng = ga.ng;
+  const int sg = ga.sg;
+  const int8_t* __restrict__ Xd = ga.Xd;
+  const int8_t* __restrict__ Vd = ga.Vd;
+  const int8_t* __restrict__ Dd = ga.Dd;
+  const double* __restrict__ vs = ga.vs;
+  const double* __restrict__ ds = ga.ds;
+  const double* __restrict__ tpar = ga.tpar;
+  const double* __restrict__ sstat = ga.sstat;
+  const uint32_t flags = ga.flags;
+  const CellOut& out = ga.out;
+  using GT = GridTiles<PL>;
+  constexpr int NV = PL + 1, NT = GT::NT, FA = GT::FA, LPW = GT::LPW;
+  static_assert(GR_SLOT >= GT::FS * 1024, "slot size");
+  __shared__ __attribute__((aligned(1024))) int8_t smem0[GR_SLOT];
+  __shared__ __attribute__((aligned(1024))) int8_t smem1[GR_SLOT];
+  __shared__ __attribute__((aligned(1024))) int8_t smem2[GR_SLOT];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+  // work-group -> (SNP tile, trait group): XCD x owns SNP tiles [x gs, x gs + gs)
+  const int64_t xcd = bid % 8, idx = bid / 8, gs = (ns + 7) / 8;
+  const int64_t c = idx / (sg * ng), base = c * sg * ng, cs = min((int64_t)sg, gs - c * sg);
+  if (cs <= 0) return;
+  const int64_t rem = idx - base, tg = rem / cs, sl = c * sg + rem % cs, st = xcd * gs + sl;
+  if (tg >= ng || sl >= gs || st >= ns) return;
+  const int64_t i0 = st * 128, j0 = tg * 32;
+  const int64_t xplane = mbp * np, vplane = tp * NV * np, dplane = tp * np;
+  const int KT = (int)(np / 32);
+  const uint32_t loff = 32 * (lane & 31) + 16 * (lane >> 5);
+  const int64_t vgrp = (j0 >> 5) * 32 * NV;  // first operand row of the trait group
+
+  v16i acc[NT][4];
+#pragma unroll
+  for (int q = 0; q < NT; ++q)
+#pragma unroll
+    for (int g = 0; g < 4; ++g) acc[q][g] = (v16i){};
+
+  auto slot = [&](auto u) -> int8_t* {
+    if constexpr (decltype(u)::value == 0) return smem0;
+    else if constexpr (decltype(u)::value == 1) return smem1;
+    else return smem2;
+  };
+  using U0 = std::integral_constant<int, 0>;
+  using U1 = std::integral_constant<int, 1>;
+  using U2 = std::integral_constant<int, 2>;
+
+  {
+    // slice s into slot u: fragment q * 4 + w of the slice, for q < LPW.  The
+    // source is a wave-uniform base plus the lane's offset into the fragment.
+    auto issue = [&](auto u, int s) {
+      int8_t* dst = slot(u);
+#pragma unroll
+      for (int q = 0; q < LPW; ++q) {
+        const int8_t* src;
+        if (q < FA / 4) {  // digit plane q of x (q < 4) or q - 4 of x o x, SNP row tile w
+          src = Xd + q * xplane + ((int64_t)s * mbp + i0 + 32 * w) * 32;
+        } else {  // entry e of the trait operand (d for e = PL + 1), plane w
+          const int e = q - FA / 4;
+          if (e <= PL)
+            src = Vd + w * vplane + ((int64_t)s * tp * NV + vgrp + 32 * e) * 32;
+          else
+            src = Dd + w * dplane + ((int64_t)s * tp + j0) * 32;
+        }
+        __builtin_amdgcn_global_load_lds(src + loff, (lds_ptr_t)(dst + (q * 4 + w) * 1024), 16, 0, 0);
+      }
+    };
+    // As the rotation's ring: wait for this wave's loads of slice s (the next
+    // slice's stay in flight), barrier (every wave's loads of s have landed,
+    // every wave is done with slice s - 1), load slice s + 2 into the slot of
+    // s - 1, multiply slice s.  Past the last slice the load repeats slice
+    // KT - 1 into a slot that is not read again (in bounds).
+    auto step = [&](auto u, int s) {
+      wait_vm<LPW>();
+      lds_barrier();
+      const int8_t* sp = slot(u) + 16 * lane;
+      v4i xa[4], xq[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
+        xq[p] = *(const v4i*)(sp + (16 + p * 4 + w) * 1024);
+      }
+      issue(std::integral_constant<int, (decltype(u)::value + 2) % 3>{}, min(s + 2, KT - 1));
+#pragma unroll
+      for (int tt = 0; tt < NT; ++tt) {
+        v4i b[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + (FA + 4 * tt + p) * 1024);
+        const v4i* a = tt == NT - 1 ? xq : xa;
+        v16i(&A)[4] = acc[tt];
+        A[0] = mfma32_i8(a[0], b[0], A[0]);
+        A[1] = mfma32_i8(a[0], b[1], A[1]);
+        A[2] = mfma32_i8(a[0], b[2], A[2]);
+        A[3] = mfma32_i8(a[0], b[3], A[3]);
+        A[1] = mfma32_i8(a[1], b[0], A[1]);
+        A[2] = mfma32_i8(a[1], b[1], A[2]);
+        A[3] = mfma32_i8(a[1], b[2], A[3]);
+        A[2] = mfma32_i8(a[2], b[0], A[2]);
+        A[3] = mfma32_i8(a[2], b[1], A[3]);
+        A[3] = mfma32_i8(a[3], b[0], A[3]);
+      }
+    };
+    issue(U0{}, 0);
+    issue(U1{}, min(1, KT - 1));
+    int s = 0;
+    for (; s + 3 <= KT; s += 3) {
+      step(U0{}, s);
+      step(U1{}, s + 1);
+      step(U2{}, s + 2);
+    }
+    if (s < KT) step(U0{}, s);
+    if (s + 1 < KT) step(U1{}, s + 1);
+    wait_vm<0>();     // no load is left in flight
+    __syncthreads();  // the ring is free: the epilogue reuses it
+  }
+
+  // per-lane trait (column lane % 32 of every tile) and its parameters
+  const int64_t j = j0 + (lane & 31);
+  const bool jok = j < t;
+  const int64_t jj = jok ? j : 0;
+  const double* tpj = tpar + jj * trait_stride(PL);
+
+  // ---- epilogue.  LDS after the K loop: slot 0 stages b, slot 1 SE, slot 2
+  // the flags and the work-group's per-SNP tables; wave w owns [32 traits][33]
+  // of each stage, so the stages need no work-group barrier.
+  constexpr int FLG_BYTES = 4 * GR_STAGE;
+  static_assert(FLG_BYTES + 128 * (2 + PL) * 8 <= GR_SLOT, "stage size");
+  double* gxT = (double*)(smem2 + FLG_BYTES);  // [128] max |x~| of the SNP
+  double* flT = gxT + 128;                     // [128] SNP flag
+  double* gmT = flT + 128;                     // [128][PL] centring coefficients (full vector)
+  const int64_t ss = snp_stride(PL);
+  if (tid < 128) {
+    const int64_t i = i0 + tid;
+    const bool iok = i < m_blk;
+    gxT[tid] = iok ? sstat[i * ss + 2 * PL + 2] : 0.0;
+    flT[tid] = iok ? sstat[i * ss + 2 * PL + 1] : 0.0;
+    if constexpr (FULL)
+#pragma unroll
+      for (int q = 0; q < PL; ++q) gmT[tid * PL + q] = iok ? sstat[i * ss + PL + q] : 0.0;
+  }
+  __syncthreads();
+
+  // trait parameters of this lane
+  double sc[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) sc[tt] = (tt <= PL ? vs[jj * NV + tt] : ds[jj]) * (1.0 / 127.0);
+  const double s2 = tpj[PL * PL + PL];
+  const bool want_p = out.pval != nullptr;
+  double* sb = (double*)smem0 + w * GR_STAGE;
+  double* sse = (double*)smem1 + w * GR_STAGE;
+  uint8_t* sfl = (uint8_t*)smem2 + w * GR_STAGE;  // [32][33] bytes per wave
+  const int64_t iw = i0 + 32 * w;
+
+  // cell r of this lane: SNP row 8 (r / 4) + 4 (lane / 32) + r % 4 of the
+  // wave's tile, trait j; solved in FP64 and staged
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int rw = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), rl = 32 * w + rw;
+    const double gx = gxT[rl];
+    double cc = 0.0, rr = 0.0, a = 0.0;
+    double cv[FULL ? PL : 1];
+#pragma unroll
+    for (int e = 0; e < NT; ++e) {
+      const double raw = g32_value(acc[e], r) * sc[e];
+      if (e < PL) {
+        const double v = raw * gx;
+        cc += v * v;
+        if constexpr (FULL) cv[e] = v;
+      } else if (e == PL) {
+        rr = raw * gx;
+      } else {
+        a = raw * gx * gx;
+      }
+    }
+    const CellResult res = cell_solve(cc, rr, a, s2, (int)flT[rl], flags, false);
+    const int so = (lane & 31) * 33 + rw;
+    sb[so] = res.b;
+    sse[so] = res.se;
+    sfl[so] = (uint8_t)res.flag;
+    if constexpr (FULL) {
+      // b_cov = u - (L^{-T} c' + gamma) b_snp (the last term undoes the
+      // centring), written in place (the full vector is not staged)
+      const int64_t i = iw + rw;
+      if (jok && i < m_blk) {
+        const int64_t o = (i + j * out.ldo) * (PL + 1);
+#pragma unroll
+        for (int q = 0; q < PL; ++q) {
+          double lc = 0.0;
+#pragma unroll
+          for (int l = 0; l < PL; ++l) lc += tpj[l * PL + q] * cv[l];
+          const double bq = res.flag ? __builtin_nan("") : tpj[PL * PL + q] - (lc + gmT[rl * PL + q]) * res.b;
+          if (out.f64) ((double*)out.b)[o + q] = bq;
+          else ((float*)out.b)[o + q] = (float)bq;
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);  // one cell at a time
+  }
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's stage writes are done
+  __builtin_amdgcn_wave_barrier();
+
+  // stores, trait row by trait row: half-wave h writes 32 consecutive SNPs of trait 2 it + h
+  const int64_t bstride = FULL ? PL + 1 : 1, boff = FULL ? PL : 0;
+#pragma unroll 4
+  for (int it = 0; it < 16; ++it) {
+    const int tr = 2 * it + (lane >> 5), sn = lane & 31;
+    const int64_t i = iw + sn, jt = j0 + tr;
+    if (i < m_blk && jt < t) {
+      const int64_t o = i + jt * out.ldo;
+      const int so = tr * 33 + sn;
+      const double bv = sb[so], sv = sse[so];
+      const uint8_t fv = sfl[so];
+      // the p-value as store_snp forms it, from the staged b and SE
+      const double pv = fv ? __builtin_nan("") : erfc(fabs(bv / sv) * M_SQRT1_2);
+      if (out.f64) {
+        ((double*)out.b)[o * bstride + boff] = bv;
+        ((double*)out.se)[o] = sv;
+        if (want_p) ((double*)out.pval)[o] = pv;
+      } else {
+        ((float*)out.b)[o * bstride + boff] = (float)bv;
+        ((float*)out.se)[o] = (float)sv;
+        if (want_p) ((float*)out.pval)[o] = (float)pv;
+      }
+      if (out.flags) out.flags[o] = fv;
+    }
+  }
+}
+
+template <int PL, bool FULL>
+__global__ void __launch_bounds__(256, 1) k_grid_ring(GridArgs a) {
+  grid_tile<PL, FULL>(a, blockIdx.x);
+}
+
+// The grid contractions of several plans' blocks in one launch.
+template <int PL, bool FULL>
+__global__ void __launch_bounds__(256, 1) k_grid_ring_batch(BatchArgs<GridArgs> B) {
+  const int64_t b = blockIdx.x;
+  const int k = batch_plan(B, b);
+  grid_tile<PL, FULL>(B.a[k], b - B.start[k]);
+}
+
+// Work-groups of the ring grid kernel for a block of m_blk SNPs: 128-SNP
+// tiles spread over the 8 XCDs in contiguous ranges, sg of them walked
+// together over every 32-trait group.
+hipError_t launch_grid_ring(const Plan& p, int64_t m_blk, const CellOut& out) {
+  const Workspace& W = p.ws;
+  const int64_t ns = (m_blk + 127) / 128, ng = (p.t + 31) / 32, gs = (ns + 7) / 8;
+  const int sg = p.grid_xt ? p.grid_xt : 4;
+  const dim3 grid((unsigned)(8 * gs * ng));
+  const bool full = (p.flags & CLAK_OUT_FULL) != 0;
+  const GridArgs ga{p.n_pad, m_blk, p.mb_pad, p.t, p.t_pad, ns, ng, sg, W.Xd, W.Vd, W.Dd, W.vs, W.ds, W.tpar, W.sstat,
+                    p.flags, out};
+#define CLAK_GR(PLV, F) k_grid_ring<PLV, F><<<grid, 256, 0, p.stream>>>(ga)
+#define CLAK_GRP(PLV)     \
+  case PLV:               \
+    if (full)             \
+      CLAK_GR(PLV, true); \
+    else                  \
+      CLAK_GR(PLV, false); \
+    break;
+  switch (p.pL) {
+    CLAK_GRP(1) CLAK_GRP(2) CLAK_GRP(3)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef CLAK_GRP
+#undef CLAK_GR
+  return hipGetLastError();
+}
+
+bool batch_compatible(const Plan& a, const Plan& b) {
+  auto ok = [](const Plan& p) {
+    return p.prec == CLAK_PREC_MIXED && !p.fused_t1 && p.pL <= 3 && p.grid_tt == 0 &&
+           !(p.flags & CLAK_STAGE_GENOTYPES);
+  };
+  return ok(a) && ok(b) && a.pL == b.pL && (a.flags & CLAK_OUT_FULL) == (b.flags & CLAK_OUT_FULL) &&
+         a.device == b.device;
+}
+
+hipError_t launch_grid_batch(const BatchItem* it, int count, hipStream_t st) {
+  if (count < 1 || count > MAX_BATCH) return hipErrorInvalidValue;
+  BatchArgs<GridArgs> B{};
+  B.count = count;
+  for (int k = 0; k < count; ++k) {
+    const Plan& p = *it[k].p;
+    const Workspace& W = p.ws;
+    const Slot& S = W.slot[it[k].slot];
+    const int64_t ns = (it[k].m_blk + 127) / 128, ng = (p.t + 31) / 32, gs = (ns + 7) / 8;
+    const int sg = p.grid_xt ? p.grid_xt : 4;
+    B.a[k] = GridArgs{p.n_pad, it[k].m_blk, p.mb_pad, p.t, p.t_pad, ns, ng, sg, S.Xd, W.Vd, W.Dd, W.vs, W.ds, W.tpar,
+                      S.sstat, p.flags, it[k].out};
+    B.start[k + 1] = B.start[k] + 8 * gs * ng;
+  }
+  const dim3 grid((unsigned)B.start[count]);
+  const bool full = (it[0].p->flags & CLAK_OUT_FULL) != 0;
+  switch (it[0].p->pL) {
+#define CLAK_GB(PLV)                                                                                  \
+  case PLV:                                                                                           \
+    full ? k_grid_ring_batch<PLV, true><<<grid, 256, 0, st>>>(B) : k_grid_ring_batch<PLV, false><<<grid, 256, 0, st>>>(B); \
+    break;
+    CLAK_GB(1) CLAK_GB(2) CLAK_GB(3)
+#undef CLAK_GB
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace clak

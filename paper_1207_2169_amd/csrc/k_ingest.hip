@@ -4,6 +4,8 @@
 // degeneracy flag).
 #include <hip/hip_fp16.h>
 
+#include <algorithm>
+
 #include "common.hpp"
 
 namespace clak {
@@ -25,19 +27,34 @@ constexpr int ING_WAVES = 8;
 // (byte c of 0x00010302 is the value of code c: 2, 3, 1, 0)
 __device__ __forceinline__ uint8_t p2_value(uint32_t code) { return (uint8_t)((0x00010302u >> (8 * code)) & 0xffu); }
 
+// Arguments of the ingest of one plan's block (S: individual windows split
+// over S work-groups per 64 SNPs).
+struct IngArgs {
+  int64_t n, np, m_blk, m_pad, mbp;
+  const void* G;
+  int64_t ldg;
+  const double* QL;
+  int8_t* Gp;
+  double* ipart;
+  int S;
+};
+
+// Work-group (bx, s0): SNPs 64 bx .., windows s0, s0 + S, ...
 template <int PL, int ALIGN, int KIND>
-__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np, int64_t m_blk, int64_t m_pad,
-                                                           int64_t mbp, const void* __restrict__ G, int64_t ldg,
-                                                           const double* __restrict__ QL, int8_t* __restrict__ Gp,
-                                                           double* __restrict__ ipart) {
+__device__ __forceinline__ void ingest_tile(const IngArgs& ia, int64_t bx, int64_t s0) {
+  const int64_t n = ia.n, np = ia.np, m_blk = ia.m_blk, m_pad = ia.m_pad, mbp = ia.mbp, ldg = ia.ldg;
+  const void* __restrict__ G = ia.G;
+  const double* __restrict__ QL = ia.QL;
+  int8_t* __restrict__ Gp = ia.Gp;
+  double* __restrict__ ipart = ia.ipart;
   constexpr int NV = PL + 2;  // v, gg, bad
   constexpr int WIN = 16 * ING_WAVES;
   __shared__ double red[ING_WAVES][64][NV + 1];
   __shared__ __attribute__((aligned(16))) double qs[PL][WIN];
   const int lane = threadIdx.x & 63;
   const int wid = threadIdx.x >> 6;
-  const int64_t snp = (int64_t)blockIdx.x * 64 + lane;
-  const int64_t S = gridDim.y, s0 = blockIdx.y;
+  const int64_t snp = bx * 64 + lane;
+  const int64_t S = ia.S;
   double acc[PL];
 #pragma unroll
   for (int a = 0; a < PL; ++a) acc[a] = 0.0;
@@ -119,17 +136,43 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(int64_t n, int64_t np
   }
 }
 
+template <int PL, int ALIGN, int KIND>
+__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(IngArgs a) {
+  ingest_tile<PL, ALIGN, KIND>(a, blockIdx.x, blockIdx.y);
+}
+
+// The ingests of several plans' blocks in one launch (per plan m_pad / 64 x S
+// work-groups, flattened).
+template <int PL, int ALIGN, int KIND>
+__global__ void __launch_bounds__(64 * ING_WAVES) k_ingest_batch(BatchArgs<IngArgs> B) {
+  const int64_t b = blockIdx.x;
+  const int k = batch_plan(B, b);
+  const int64_t l = b - B.start[k];
+  ingest_tile<PL, ALIGN, KIND>(B.a[k], l / B.a[k].S, l % B.a[k].S);
+}
+
 // Pass 2, one thread per SNP: sums the S partials in a fixed order and writes
 //   v = Q_L^T g, gamma = R^{-1} v, ||g - Q_L v|| = sqrt(gg - ||v||^2), and
 //   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
 //   (gg == 0 or ||g - Q_L v||^2 <= 1e-10 gg); else 0.
 // SNP rows in [m_blk, m_pad) become zero SNPs with flag 1.
+struct FinArgs {
+  int64_t m_blk, m_pad, mbp;
+  int S;
+  const double* ipart;
+  const double* Rinv;
+  double* sstat;
+};
+
 template <int PL>
-__global__ void __launch_bounds__(256) k_ingest_fin(int64_t m_blk, int64_t m_pad, int64_t mbp, int S,
-                                                    const double* __restrict__ ipart, const double* __restrict__ Rinv,
-                                                    double* __restrict__ sstat) {
+__device__ __forceinline__ void ingest_fin_tile(const FinArgs& fa, int64_t bx) {
+  const int64_t m_blk = fa.m_blk, m_pad = fa.m_pad, mbp = fa.mbp;
+  const int S = fa.S;
+  const double* __restrict__ ipart = fa.ipart;
+  const double* __restrict__ Rinv = fa.Rinv;
+  double* __restrict__ sstat = fa.sstat;
   constexpr int NV = PL + 2;
-  const int64_t snp = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t snp = bx * 256 + threadIdx.x;
   if (snp >= m_pad) return;
   double t[NV];
 #pragma unroll
@@ -158,29 +201,37 @@ __global__ void __launch_bounds__(256) k_ingest_fin(int64_t m_blk, int64_t m_pad
 }
 
 template <int PL>
+__global__ void __launch_bounds__(256) k_ingest_fin(FinArgs a) {
+  ingest_fin_tile<PL>(a, blockIdx.x);
+}
+
+template <int PL>
+__global__ void __launch_bounds__(256) k_ingest_fin_batch(BatchArgs<FinArgs> B) {
+  const int64_t b = blockIdx.x;
+  const int k = batch_plan(B, b);
+  ingest_fin_tile<PL>(B.a[k], b - B.start[k]);
+}
+
+template <int PL>
 static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const void* d_G, int g_dtype, int64_t ldg) {
   const int S = ingest_splits(p);
   dim3 grid((unsigned)(m_pad / 64), (unsigned)S);
   const Workspace& W = p.ws;
   const dim3 block(64 * ING_WAVES);
+  const IngArgs ia{p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, W.ipart, S};
   if (g_dtype == CLAK_G_F16) {
-    k_ingest<PL, 1, 1><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
-                                                     W.ipart);
+    k_ingest<PL, 1, 1><<<grid, block, 0, p.stream>>>(ia);
   } else if (g_dtype == CLAK_G_P2) {
     const bool words = ((uintptr_t)d_G % 4 == 0) && (ldg % 4 == 0);
     if (words)
-      k_ingest<PL, 4, 2><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
-                                                       W.ipart);
+      k_ingest<PL, 4, 2><<<grid, block, 0, p.stream>>>(ia);
     else
-      k_ingest<PL, 1, 2><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp,
-                                                       W.ipart);
+      k_ingest<PL, 1, 2><<<grid, block, 0, p.stream>>>(ia);
   } else {
     // widest alignment shared by the base address and the row pitch, capped at 16
     const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
     const int align = (int)(bits & (~bits + 1));
-#define CLAK_ING(A)                                                                                               \
-  k_ingest<PL, A, 0><<<grid, block, 0, p.stream>>>(p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, \
-                                                   W.ipart)
+#define CLAK_ING(A) k_ingest<PL, A, 0><<<grid, block, 0, p.stream>>>(ia)
     if (align >= 16)
       CLAK_ING(16);
     else if (align >= 8)
@@ -191,8 +242,61 @@ static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const v
       CLAK_ING(1);
 #undef CLAK_ING
   }
-  k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv,
-                                                                        W.sstat);
+  k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(
+      FinArgs{m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv, W.sstat});
+}
+
+template <int PL>
+static hipError_t ingest_batch_pl(const BatchItem* it, int count, int g_dtype, hipStream_t st) {
+  BatchArgs<IngArgs> B{};
+  BatchArgs<FinArgs> F{};
+  B.count = F.count = count;
+  int align = 16;
+  bool words = true;
+  for (int k = 0; k < count; ++k) {
+    const Plan& p = *it[k].p;
+    const Slot& S = p.ws.slot[it[k].slot];
+    const int64_t m_pad = roundup(it[k].m_blk, SNP_PAD);
+    const int sp = ingest_splits(p);
+    B.a[k] = IngArgs{p.n, p.n_pad, it[k].m_blk, m_pad, p.mb_pad, it[k].G, it[k].ldg, p.ws.QL, S.Gp, S.ipart, sp};
+    F.a[k] = FinArgs{it[k].m_blk, m_pad, p.mb_pad, sp, S.ipart, p.ws.Rinv, S.sstat};
+    B.start[k + 1] = B.start[k] + m_pad / 64 * sp;
+    F.start[k + 1] = F.start[k] + m_pad / 256;
+    const uint64_t bits = (uint64_t)(uintptr_t)it[k].G | (uint64_t)it[k].ldg | 16u;
+    align = std::min(align, (int)(bits & (~bits + 1)));
+    words = words && ((uintptr_t)it[k].G % 4 == 0) && (it[k].ldg % 4 == 0);
+  }
+  const dim3 grid((unsigned)B.start[count]), block(64 * ING_WAVES);
+  if (g_dtype == CLAK_G_F16)
+    k_ingest_batch<PL, 1, 1><<<grid, block, 0, st>>>(B);
+  else if (g_dtype == CLAK_G_P2)
+    words ? k_ingest_batch<PL, 4, 2><<<grid, block, 0, st>>>(B) : k_ingest_batch<PL, 1, 2><<<grid, block, 0, st>>>(B);
+  else if (align >= 16)
+    k_ingest_batch<PL, 16, 0><<<grid, block, 0, st>>>(B);
+  else if (align >= 8)
+    k_ingest_batch<PL, 8, 0><<<grid, block, 0, st>>>(B);
+  else if (align >= 4)
+    k_ingest_batch<PL, 4, 0><<<grid, block, 0, st>>>(B);
+  else
+    k_ingest_batch<PL, 1, 0><<<grid, block, 0, st>>>(B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_ingest_fin_batch<PL><<<dim3((unsigned)F.start[count]), 256, 0, st>>>(F);
+  return hipGetLastError();
+}
+
+hipError_t launch_ingest_batch(const BatchItem* it, int count, int g_dtype, hipStream_t st) {
+  if (count < 1 || count > MAX_BATCH) return hipErrorInvalidValue;
+  switch (it[0].p->pL) {
+    case 1:
+      return ingest_batch_pl<1>(it, count, g_dtype, st);
+    case 2:
+      return ingest_batch_pl<2>(it, count, g_dtype, st);
+    case 3:
+      return ingest_batch_pl<3>(it, count, g_dtype, st);
+    default:
+      return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg) {

@@ -51,13 +51,6 @@ constexpr int LROW = 80;  // LDS row pitch in bytes for 64-byte K slices (bank-c
 //          centred by C = Q_L^T U: for them x~ is a linear cell sum (c', then
 //          r') of the SNP, which goes to the SNP's statistics.
 //
-// v_mfma_i32_32x32x32_i8 lane layout (gfx950): lane l supplies 16 bytes of row
-// l%32 of A and of column l%32 of B, the same 16 values of the 32-deep
-// contraction (half l/32); result register r holds C[8(r/4) + 4(l/32) + r%4][l%32].
-__device__ __forceinline__ v16i mfma32_i8(v4i a, v4i b, v16i c) {
-  return __builtin_amdgcn_mfma_i32_32x32x32_i8(a, b, c, 0, 0, 0);
-}
-
 // Waves per SIMD the register budget is cut for: three for the one-column-tile
 // configuration (64 accumulation registers), else one or two.
 template <int PL, int EPI, int CT>
@@ -65,31 +58,29 @@ constexpr int rot_waves() {
   return CT == 1 ? (PL <= 4 ? 3 : 2) : ((CT > 2 || (EPI == 1 && PL > 3)) ? 1 : 2);
 }
 
-// Encoded s_waitcnt immediate that waits until at most N vector memory
-// operations of the wave are outstanding (expcnt and lgkmcnt not waited on).
-template <int N>
-__device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
+// Arguments of the rotation of one plan's block (see rot_tile).
+struct RotArgs {
+  int64_t np, nz, zl, mb, mbp, ntn;
+  int rg, tri;
+  const int8_t* Zd;
+  const double* zs;
+  const int8_t* Gp;
+  const double* Qt;
+  const double* Cq;
+  double* sstat;
+  double* X;
+  const double* Dv;
+  double* part;
+};
 
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
-// Work-group barrier for the direct-load ring: the wave's LDS reads complete
-// (lgkmcnt 0), then s_barrier.  Unlike __syncthreads it does not wait for
-// the wave's outstanding global-to-LDS loads; the caller waits for the ones
-// it needs (wait_vm) before the barrier.  The memory clobbers keep the
-// compiler from moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
+// Work-group bid of the rotation grid of one plan's block.
 template <int PL, int EPI, int CT, int WR, int WC, int DL>
-__global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
-    k_rot_i8(int64_t np, int64_t nz, int64_t zl, int64_t mb, int64_t mbp, int64_t ntn, int rg, int tri,
-             const int8_t* __restrict__ Zd, const double* __restrict__ zs, const int8_t* __restrict__ Gp,
-             const double* __restrict__ Qt, const double* __restrict__ Cq, double* __restrict__ sstat,
-             double* __restrict__ X, const double* __restrict__ Dv, double* __restrict__ part) {
+__device__ __forceinline__ void rot_tile(int64_t np, int64_t nz, int64_t zl, int64_t mb, int64_t mbp, int64_t ntn,
+                                         int rg, int tri, const int8_t* __restrict__ Zd,
+                                         const double* __restrict__ zs, const int8_t* __restrict__ Gp,
+                                         const double* __restrict__ Qt, const double* __restrict__ Cq,
+                                         double* __restrict__ sstat, double* __restrict__ X,
+                                         const double* __restrict__ Dv, double* __restrict__ part, int64_t bid) {
   constexpr int NT = 64 * WR * WC, BM = 32 * WR, BN = 32 * CT * WC, BK = 64;
   constexpr int A_STAGE = 4 * BM * LROW, B_STAGE = BN * LROW;
   constexpr int A_LD = 16 * BM / NT, B_LD = 4 * BN / NT;  // 16-byte loads per thread per slice
@@ -119,7 +110,7 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   const int wr = wid / WC, wc = wid % WC;
   const int64_t ntm = nz / BM;
   const int64_t sg = 8 / rg, gm = (ntm + rg - 1) / rg, gn = (ntn + sg - 1) / sg;
-  const int64_t xcd = blockIdx.x % 8, idx = blockIdx.x / 8;
+  const int64_t xcd = bid % 8, idx = bid / 8;
   // lower-triangular Z^T (CLAK-Chol): row tile tm needs the first tm + 1 K
   // tiles only; the row tiles of a row group are interleaved across the row
   // groups (equal work per XCD) and taken heaviest first
@@ -451,6 +442,22 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>()))
   }
 }
 
+template <int PL, int EPI, int CT, int WR, int WC, int DL>
+__global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>())) k_rot_i8(RotArgs a) {
+  rot_tile<PL, EPI, CT, WR, WC, DL>(a.np, a.nz, a.zl, a.mb, a.mbp, a.ntn, a.rg, a.tri, a.Zd, a.zs, a.Gp, a.Qt, a.Cq,
+                                    a.sstat, a.X, a.Dv, a.part, blockIdx.x);
+}
+
+// The rotations of several plans' blocks in one launch.
+template <int PL, int EPI, int CT, int WR, int WC, int DL>
+__global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>())) k_rot_i8_batch(BatchArgs<RotArgs> B) {
+  const int64_t b = blockIdx.x;
+  const int k = batch_plan(B, b);
+  const RotArgs& a = B.a[k];
+  rot_tile<PL, EPI, CT, WR, WC, DL>(a.np, a.nz, a.zl, a.mb, a.mbp, a.ntn, a.rg, a.tri, a.Zd, a.zs, a.Gp, a.Qt, a.Cq,
+                                    a.sstat, a.X, a.Dv, a.part, b - B.start[k]);
+}
+
 // Rotation tile configurations (CT 32-column MFMA tiles per wave, WR x WC
 // waves; DL: staged by direct global-to-LDS loads into a ring of three (DL3)
 // or four (DL4) K slices, two or three slices in flight and no staging
@@ -518,10 +525,23 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
 // K-tiled.  A work-group takes one 32-deep slice of 32 SNPs; eight threads
 // share a SNP (four eigen rows each), so every plane receives one contiguous
 // kilobyte per work-group.
-__global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, const double* __restrict__ X,
-                                               const double* __restrict__ sstat, int8_t* __restrict__ Xd) {
-  const int64_t i = (int64_t)blockIdx.x * 32 + (threadIdx.x >> 3);
-  const int64_t k = (int64_t)blockIdx.y * 32 + 4 * (threadIdx.x & 7);
+struct QuantArgs {
+  int64_t np, mbp, nbx;  // nbx: 32-SNP groups of the block (the work-groups along the SNPs)
+  int pL;
+  const double* X;
+  const double* sstat;
+  int8_t* Xd;
+};
+
+// Work-group (bx, by): SNPs 32 bx .., eigen rows 32 by ..
+__device__ __forceinline__ void quant_tile(const QuantArgs& a, int64_t bx, int64_t by) {
+  const int64_t np = a.np, mbp = a.mbp;
+  const int pL = a.pL;
+  const double* __restrict__ X = a.X;
+  const double* __restrict__ sstat = a.sstat;
+  int8_t* __restrict__ Xd = a.Xd;
+  const int64_t i = bx * 32 + (threadIdx.x >> 3);
+  const int64_t k = by * 32 + 4 * (threadIdx.x & 7);
   const int64_t xplane = mbp * np;
   const double mx = sstat[i * snp_stride(pL) + 2 * pL + 2];
   const double inv = mx > 0.0 ? 1.0 / mx : 0.0, inv2 = inv * inv;
@@ -541,6 +561,17 @@ __global__ void __launch_bounds__(256) k_quant(int64_t np, int64_t mbp, int pL, 
   const int64_t off = kt32(i, k, mbp);
 #pragma unroll
   for (int q = 0; q < 8; ++q) *(int32_t*)(Xd + q * xplane + off) = pk[q];
+}
+
+__global__ void __launch_bounds__(256) k_quant(QuantArgs a) { quant_tile(a, blockIdx.x, blockIdx.y); }
+
+// The encodings of several plans' blocks in one launch (grid flattened per
+// plan: nbx x n_pad / 32 work-groups).
+__global__ void __launch_bounds__(256) k_quant_batch(BatchArgs<QuantArgs> B) {
+  const int64_t b = blockIdx.x;
+  const int k = batch_plan(B, b);
+  const int64_t l = b - B.start[k];
+  quant_tile(B.a[k], l % B.a[k].nbx, l / B.a[k].nbx);
 }
 
 // Ring depth actually used: a four-slot ring whose LDS (slots, the larger
@@ -568,8 +599,8 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
   dim3 block(64 * WR * WC);
 #define CLAK_ROT(PLV, EPI, XP, DP, PP)                                                                         \
   case PLV:                                                                                                        \
-    k_rot_i8<PLV, EPI, CT, WR, WC, rot_ring<PLV, EPI, CT, WR, WC, DL>()><<<grid, block, 0, p.stream>>>(          \
-        p.n_pad, p.zrows, p.zlin, m_blk, p.mb_pad, ntn, rg, tri, W.Zd, W.zs, W.Gp, W.Qt, W.Cq, W.sstat, XP, DP, PP); \
+    k_rot_i8<PLV, EPI, CT, WR, WC, rot_ring<PLV, EPI, CT, WR, WC, DL>()><<<grid, block, 0, p.stream>>>(RotArgs{    \
+        p.n_pad, p.zrows, p.zlin, m_blk, p.mb_pad, ntn, rg, tri, W.Zd, W.zs, W.Gp, W.Qt, W.Cq, W.sstat, XP, DP, PP}); \
     break;
   if (p.fused_t1) {
     switch (p.pL) {
@@ -618,10 +649,63 @@ hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
   }
 }
 
+// Batched rotations of several multi-trait plans' blocks, with the built-in
+// tiles of such plans (64 x 128, direct loads into a three-slot ring); each
+// plan keeps its own XCD row grouping.
+template <int PL>
+static hipError_t rotate_batch_pl(const BatchItem* it, int count, hipStream_t st) {
+  constexpr int CT = 2, WR = 2, WC = 2, DL = 3, BN = 32 * CT * WC;
+  BatchArgs<RotArgs> B{};
+  B.count = count;
+  for (int k = 0; k < count; ++k) {
+    const Plan& p = *it[k].p;
+    const Slot& S = p.ws.slot[it[k].slot];
+    const int64_t ntn = roundup(it[k].m_blk, SNP_PAD) / BN, ntm = p.zrows / ROT_BM;
+    const int rg = p.rot_rg ? p.rot_rg : rot_rg_builtin(p);
+    const int64_t gm = (ntm + rg - 1) / rg, gn = (ntn + 8 / rg - 1) / (8 / rg);
+    B.a[k] = RotArgs{p.n_pad, p.zrows, p.zlin, it[k].m_blk, p.mb_pad, ntn, rg, 0, p.ws.Zd, p.ws.zs, S.Gp, p.ws.Qt,
+                     p.ws.Cq, S.sstat, S.X64, nullptr, nullptr};
+    B.start[k + 1] = B.start[k] + 8 * gm * gn;
+  }
+  k_rot_i8_batch<PL, 0, CT, WR, WC, rot_ring<PL, 0, CT, WR, WC, DL>()>
+      <<<dim3((unsigned)B.start[count]), dim3(64 * WR * WC), 0, st>>>(B);
+  return hipGetLastError();
+}
+
+hipError_t launch_rotate_batch(const BatchItem* it, int count, hipStream_t st) {
+  if (count < 1 || count > MAX_BATCH) return hipErrorInvalidValue;
+  switch (it[0].p->pL) {
+    case 1:
+      return rotate_batch_pl<1>(it, count, st);
+    case 2:
+      return rotate_batch_pl<2>(it, count, st);
+    case 3:
+      return rotate_batch_pl<3>(it, count, st);
+    default:
+      return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_encode_batch(const BatchItem* it, int count, hipStream_t st) {
+  if (count < 1 || count > MAX_BATCH) return hipErrorInvalidValue;
+  BatchArgs<QuantArgs> B{};
+  B.count = count;
+  for (int k = 0; k < count; ++k) {
+    const Plan& p = *it[k].p;
+    const Slot& S = p.ws.slot[it[k].slot];
+    const int64_t nbx = (it[k].m_blk + 31) / 32;
+    B.a[k] = QuantArgs{p.n_pad, p.mb_pad, nbx, (int)p.pL, S.X64, S.sstat, S.Xd};
+    B.start[k + 1] = B.start[k] + nbx * (p.n_pad / 32);
+  }
+  k_quant_batch<<<dim3((unsigned)B.start[count]), 256, 0, st>>>(B);
+  return hipGetLastError();
+}
+
 hipError_t launch_encode(const Plan& p, int64_t m_blk) {
   if (p.prec != CLAK_PREC_MIXED || p.fused_t1) return hipSuccess;
   dim3 qgrid((unsigned)((m_blk + 31) / 32), (unsigned)(p.n_pad / 32));
-  k_quant<<<qgrid, 256, 0, p.stream>>>(p.n_pad, p.mb_pad, (int)p.pL, p.ws.X64, p.ws.sstat, p.ws.Xd);
+  k_quant<<<qgrid, 256, 0, p.stream>>>(
+      QuantArgs{p.n_pad, p.mb_pad, (m_blk + 31) / 32, (int)p.pL, p.ws.X64, p.ws.sstat, p.ws.Xd});
   return hipGetLastError();
 }
 // ------------------------------------------------------------------ grid
@@ -781,9 +865,6 @@ __device__ __forceinline__ void g32_stage(v16i (&acc)[4][4], const int8_t* As, c
   }
 }
 
-__device__ __forceinline__ double g32_value(const v16i (&acc)[4], int r) {
-  return (((double)acc[0][r] * 256.0 + (double)acc[1][r]) * 256.0 + (double)acc[2][r]) * 256.0 + (double)acc[3][r];
-}
 
 // One pass over K into NT accumulator tiles.  Lane l of wave w stages row
 // 32 w + l % 32, half l / 32, of each 32-row group: the same lane pattern as
@@ -967,6 +1048,9 @@ hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out) {
 hipError_t launch_grid_mixed(const Plan& p, int64_t m_blk, const CellOut& out) {
   const Workspace& W = p.ws;
   if (p.fused_t1) return launch_fin_t1(p, m_blk, out);
+  // built-in for p_L <= 3: the one-pass ring kernel (k_grid.hip); grid_tt =
+  // 32 or 64 selects the two-stage kernel below
+  if (p.grid_tt == 0 && p.pL <= 3) return launch_grid_ring(p, m_blk, out);
   if (p.pL <= 3 || !(p.flags & CLAK_OUT_FULL)) {
     // traits per work-group: 64 unless 32 gives fewer modelled
     // dispatch rounds of 256 work-groups x traits per tile

@@ -51,6 +51,78 @@ __global__ void k_split_digits(int64_t n, int64_t np, int64_t zr, int64_t zl, in
   if (threadIdx.x == 0) zs[k] = mx / QMAX;
 }
 
+// Replaces rows [r0, r1) of the rotation operand by the values their digit
+// planes encode (zs[k] * sum_p d_p 256^(3-p)).  Used for the single-trait
+// rows U^T: C = Q_L^T U is then formed from the matrix the int8 rotation
+// multiplies by, so the centring of those rows cancels their digit rounding.
+__global__ void k_dequant_rows(int64_t np, int64_t zr, int64_t r0, const int8_t* __restrict__ Zd,
+                               const double* __restrict__ zs, double* __restrict__ Zt) {
+  const int64_t k = r0 + blockIdx.x;
+  const int64_t plane = zr * np;
+  const double sc = zs[k];
+  for (int64_t i = threadIdx.x; i < np; i += blockDim.x) {
+    const int64_t o = kt32(k, i, zr);
+    const int q = (((int)Zd[o] * 256 + (int)Zd[plane + o]) * 256 + (int)Zd[2 * plane + o]) * 256 +
+                  (int)Zd[3 * plane + o];
+    Zt[k * np + i] = sc * (double)q;
+  }
+}
+
+// The centring rotation of the mixed path, Qt = Z_q^T Q_L with Z_q the values
+// the digit planes of Z^T encode (one work-group per row k; FP64).  A rotated
+// SNP is x~ = Z_q^T g - Qt v: with the same Z_q on both sides, the centring
+// cancels the digit rounding of Z_q^T g up to FP64 rounding, so the error of
+// x~ is relative to the centred SNP g - Q_L v, not to g (which matters for
+// SNPs close to span(X_L)).  X_L, Y and everything else are rotated by the
+// FP64 Z; the two differ by the digit rounding, about 2^-31 of each row.
+template <int PL>
+__global__ void __launch_bounds__(256) k_qt_digits(int64_t n, int64_t np, int64_t zr, const int8_t* __restrict__ Zd,
+                                                   const double* __restrict__ zs, const double* __restrict__ QL,
+                                                   double* __restrict__ Qt) {
+  __shared__ double red[8];
+  const int64_t k = blockIdx.x;
+  const int64_t plane = zr * np;
+  double acc[PL];
+#pragma unroll
+  for (int a = 0; a < PL; ++a) acc[a] = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const int64_t o = kt32(k, i, zr);
+    const double z = (double)((((int)Zd[o] * 256 + (int)Zd[plane + o]) * 256 + (int)Zd[2 * plane + o]) * 256 +
+                              (int)Zd[3 * plane + o]);
+#pragma unroll
+    for (int a = 0; a < PL; ++a) acc[a] += z * QL[i + a * np];
+  }
+  const double sc = zs[k];
+#pragma unroll
+  for (int a = 0; a < PL; ++a) {
+    const double v = block_sum(acc[a], red);
+    if (threadIdx.x == 0) Qt[k + a * np] = sc * v;
+  }
+}
+
+hipError_t launch_qt_digits(const Plan& p) {
+  const Workspace& W = p.ws;
+  const dim3 grid((unsigned)p.n_pad);
+  switch (p.pL) {
+#define CLAK_QT(PLV)                                                                                          \
+  case PLV:                                                                                                   \
+    k_qt_digits<PLV><<<grid, 256, 0, p.stream>>>(p.n, p.n_pad, p.zrows, W.Zd, W.zs, W.QL, W.Qt); \
+    break;
+    CLAK_QT(1) CLAK_QT(2) CLAK_QT(3) CLAK_QT(4) CLAK_QT(5) CLAK_QT(6) CLAK_QT(7) CLAK_QT(8)
+#undef CLAK_QT
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dequant_rows(const Plan& p, int64_t r0, int64_t r1) {
+  if (r1 <= r0) return hipSuccess;
+  k_dequant_rows<<<dim3((unsigned)(r1 - r0)), dim3(256), 0, p.stream>>>(p.n_pad, p.zrows, r0, p.ws.Zd, p.ws.zs,
+                                                                          p.ws.Zt);
+  return hipGetLastError();
+}
+
 hipError_t launch_split_digits(const Plan& p, int64_t r0, int64_t r1) {
   if (r1 <= r0) return hipSuccess;
   k_split_digits<<<dim3((unsigned)(r1 - r0)), dim3(256), 0, p.stream>>>(p.n, p.n_pad, p.zrows, p.zlin, r0, p.ws.Zt,
@@ -418,10 +490,15 @@ __global__ void __launch_bounds__(256) k_cproj(int64_t np, int64_t zl, int pL, c
   }
 }
 
+// U = Z W into rows zlin .. of Z^T, their digit planes, the rows replaced by
+// the values the digits encode, then C = Q_L^T U of those values.
 hipError_t launch_uproj(const Plan& p) {
   const Workspace& W = p.ws;
   k_uproj<<<dim3((unsigned)((p.n_pad + 255) / 256)), 256, 0, p.stream>>>(p.n, p.n_pad, p.zlin, p.zrows,
                                                                          (int)p.pL + 1, W.V64, W.Zt);
+  hipError_t e = launch_split_digits(p, p.zlin, p.zrows);
+  if (e == hipSuccess) e = launch_dequant_rows(p, p.zlin, p.zrows);
+  if (e != hipSuccess) return e;
   k_cproj<<<1, 256, 0, p.stream>>>(p.n_pad, p.zlin, (int)p.pL, W.QL, W.Zt, W.Cq);
   return hipGetLastError();
 }

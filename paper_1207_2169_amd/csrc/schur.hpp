@@ -93,4 +93,31 @@ __device__ __forceinline__ void schur_store_cc(double cc, double r, double a, co
   store_snp(out, i + j * out.ldo, bsnp, se, flag, true);
 }
 
+
+// One cell solved into registers (for kernels that stage their outputs
+// before storing them): the same arithmetic as schur_store, given ||c'||^2
+// (cc), r', a, the trait's parameters and the SNP's flag.
+struct CellResult {
+  double b, se, pv;
+  int flag;
+};
+
+__device__ __forceinline__ CellResult cell_solve(double cc, double r, double a, double s2, int snp_flag,
+                                                 uint32_t flags, bool want_p) {
+  const double nan = __builtin_nan("");
+  CellResult o;
+  o.flag = snp_flag;
+  const double s = a - cc;
+  if (o.flag == 0 && !(s > 1e-10 * a)) o.flag = CLAK_CELL_DEGENERATE;
+  o.b = nan;
+  o.se = nan;
+  o.pv = nan;
+  if (o.flag == 0) {
+    o.b = r / s;
+    o.se = sqrt((flags & CLAK_VAR_PAPER) ? s2 / s : 1.0 / s);
+    if (want_p) o.pv = erfc(fabs(o.b / o.se) * M_SQRT1_2);
+  }
+  return o;
+}
+
 }  // namespace clak

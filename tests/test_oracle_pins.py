@@ -415,3 +415,67 @@ def test_rejects_bad_arguments():
         oracle.gls_cells(Phi, XL, G, Y, h2, s2, [7], [0])
     with pytest.raises(ValueError):
         oracle.gls_cells(Phi, XL, G, Y, h2, s2, [0], [3])
+
+# --------------------------------------------------------------------------- extended-precision route
+
+
+def test_extended_precision_route_matches_the_oracle():
+    """oracle.extended (the same route in 64-bit-significand arithmetic) agrees
+    with the FP64 oracle on well-conditioned problems."""
+    from oracle import extended
+    Phi, XL, G, Y, h2, s2 = _problem(seed=40, n=50, t=3, ng=4)
+    cells = _cells(4, 3)
+    b, var, flag = oracle.gls_cells(Phi, XL, G, Y, h2, s2, *cells)
+    be, ve, fe = extended.gls_cells(Phi, XL, G, Y, h2, s2, *cells)
+    assert (flag == fe).all()
+    np.testing.assert_allclose(be, b, rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(ve, var, rtol=1e-11, atol=1e-15)
+    bp, vp, _ = extended.gls_cells(Phi, XL, G, Y, h2, s2, *cells, var_paper=True)
+    np.testing.assert_allclose(vp, ve * s2[cells[1]][:, None, None], rtol=1e-15)
+
+
+@pytest.mark.parametrize("n,seed", [(5, 14), (6, 15)])
+def test_extended_precision_route_exact_rational(n, seed):
+    """Rational inputs exactly representable in FP64: the extended route's
+    b and Var match the exact rational solution to about 2^-60."""
+    from oracle import extended
+    rng = np.random.default_rng(seed)
+    A = rng.integers(-3, 4, size=(n, n + 2))
+    Phi = [[Fraction(int(v), 8) for v in row] for row in (A @ A.T)]
+    for k in range(n):
+        Phi[k][k] += Fraction(1, 4)
+    h2, s2 = Fraction(3, 8), Fraction(5, 4)
+    XL = [[Fraction(1), Fraction(int(rng.integers(0, 2)))] for _ in range(n)]
+    g = [Fraction(int(v)) for v in rng.integers(0, 3, n)]
+    y = [Fraction(int(v), 4) for v in rng.integers(-20, 20, n)]
+    M = [[s2 * (h2 * Phi[r][c] + ((1 - h2) if r == c else 0)) for c in range(n)] for r in range(n)]
+    X = [XL[r] + [g[r]] for r in range(n)]
+    MiX = _frac_solve(M, X)
+    Miy = [row[0] for row in _frac_solve(M, [[v] for v in y])]
+    p = 3
+    S = [[sum(X[r][a] * MiX[r][c] for r in range(n)) for c in range(p)] for a in range(p)]
+    rhs = [[sum(X[r][a] * Miy[r] for r in range(n))] for a in range(p)]
+    bex = [row[0] for row in _frac_solve(S, rhs)]
+    f = lambda M_: np.array([[float(v) for v in row] for row in M_])
+    b, var, flag = extended.gls_cells(f(Phi), f(XL), np.array([[float(v)] for v in g]),
+                                      np.array([[float(v)] for v in y]), [float(h2)], [float(s2)], [0], [0])
+    assert flag[0] == 0
+    np.testing.assert_allclose(b[0], [float(v) for v in bex], rtol=4e-16)
+
+
+def test_extended_precision_route_near_collinear():
+    """At shares 1e-8 .. 2e-10 outside span(X_L) the extended route flags as
+    the FP64 oracle does and matches the numpy solve of the pin above; the
+    FP64 oracle's distance from it stays within its rounding bound
+    10 n u / share in SE units."""
+    from oracle import extended
+    rho = RHO_KEPT + RHO_FLAGGED
+    Phi, XL, G, Y, h2, s2, share = _near_collinear_snps(rho)
+    cells = (np.arange(len(rho)), np.zeros(len(rho), int))
+    b, var, flag = oracle.gls_cells(Phi, XL, G, Y, h2, s2, *cells)
+    be, ve, fe = extended.gls_cells(Phi, XL, G, Y, h2, s2, *cells)
+    assert list(fe) == list(flag)
+    n, u = Phi.shape[0], 2.0 ** -53
+    for c, q in enumerate(RHO_KEPT):
+        se = np.sqrt(ve[c, -1, -1])
+        assert abs(b[c, -1] - be[c, -1]) / se < 10 * n * u / q
