@@ -218,6 +218,30 @@ clak_status clak_run_block(clak_plan_t plan, int64_t m_blk, const void* d_G, int
                            int64_t ldg, void* d_b, void* d_se, int out_dtype, int64_t ldo,
                            uint8_t* d_flags, void* d_pval);
 
+/* For callers that cannot allocate device memory around a call (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * clak_run_block_static is clak_run_block with the block's scratch buffers
+ * (genotype panel, per-SNP statistics, partial sums, rotated SNPs and their
+ * digit planes) in a device array of the library, one per GPU, of
+ * CLAK_STATIC_SCRATCH_BYTES, instead of the plan's workspace slot.  It calls
+ * no hipMalloc, hipFree or other allocating routine (the plan, its workspace
+ * and every set-up call still have to come first).  The array keeps the last
+ * call's contents; calls on one GPU share it, so calls that overlap on one
+ * GPU (several streams, several plans) race.  Same arguments, outputs and
+ * asynchrony as clak_run_block.  Errors: as clak_run_block; CLAK_E_UNSUPPORTED
+ * when the plan's block scratch (clak_plan_block_scratch_size) exceeds the
+ * array or the plan has CLAK_STAGE_GENOTYPES; CLAK_E_STATE while the stage
+ * profiler is on; CLAK_E_DEVICE when the plan's device is not current. */
+#define CLAK_STATIC_SCRATCH_BYTES (64u << 20)
+clak_status clak_run_block_static(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg,
+                                  void* d_b, void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags,
+                                  void* d_pval);
+
+/* Bytes of scratch one SNP block of the plan needs (the size of one
+ * workspace slot): clak_run_block_static accepts the plan when this is at
+ * most CLAK_STATIC_SCRATCH_BYTES.  Errors: CLAK_E_ARG (null argument). */
+clak_status clak_plan_block_scratch_size(clak_plan_t plan, size_t* bytes);
+
 /* One SNP block of a pipeline or batch: the arguments of clak_run_block. */
 typedef struct clak_block {
   int64_t m_blk;    /* SNPs in the block, 1 <= m_blk <= max_block        */

@@ -52,6 +52,8 @@ SIGNATURES = {
     "clak_set_traits": (_I, [_P, _P, _I64, _P, _P]),
     "clak_estimate_vc": (_I, [_P, _P, _I64, _I, _P, _P, _P]),
     "clak_run_block": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, _P]),
+    "clak_run_block_static": (_I, [_P, _I64, _P, _I, _I64, _P, _P, _I, _I64, _P, _P]),
+    "clak_plan_block_scratch_size": (_I, [_P, ctypes.POINTER(_SZ)]),
     "clak_plan_destroy": (_I, [_P]),
     "clak_plan_set_profiling": (_I, [_P, _I]),
     "clak_plan_set_tuning": (_I, [_P, _I, _I, _I, _I]),
@@ -255,6 +257,21 @@ def clak_run_block(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor
     blk, gdt, odt = _block_args(clak_plan_get_shape(plan), G, b, se, flags, pval, g_dtype)
     _check(lib().clak_run_block(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo, blk.flags,
                                 blk.pval), "clak_run_block")
+
+
+def clak_run_block_static(plan: int, G: torch.Tensor, b: torch.Tensor, se: torch.Tensor,
+                          flags: Optional[torch.Tensor] = None, pval: Optional[torch.Tensor] = None,
+                          g_dtype: Optional[int] = None):
+    """clak_run_block with the block's scratch in the library's device array (no allocation)."""
+    blk, gdt, odt = _block_args(clak_plan_get_shape(plan), G, b, se, flags, pval, g_dtype)
+    _check(lib().clak_run_block_static(plan, blk.m_blk, blk.G, gdt, blk.ldg, blk.b, blk.se, odt, blk.ldo,
+                                       blk.flags, blk.pval), "clak_run_block_static")
+
+
+def clak_plan_block_scratch_size(plan: int) -> int:
+    out = _SZ()
+    _check(lib().clak_plan_block_scratch_size(plan, ctypes.byref(out)), "clak_plan_block_scratch_size")
+    return out.value
 
 
 def clak_bed_open(path: str, n: int, m: int, block: int, depth: int = 4) -> int:
