@@ -56,8 +56,10 @@ def parse():
     ap.add_argument("--stage-genotypes", action="store_true",
                     help="plan flag CLAK_STAGE_GENOTYPES: copy-engine staging of every block before the ingest")
     ap.add_argument("--no-tune", action="store_true",
-                    help="skip clak_autotune (launch parameters timed on the first block before the timed region)")
-    ap.add_argument("--tune-cache", default=None, help="clak_autotune cache file (default: none, always time)")
+                    help="skip clak_autotune_pipeline (launch parameters timed on a pipelined pass over the first "
+                         "blocks before the timed region)")
+    ap.add_argument("--tune-blocks", type=int, default=4, help="blocks of the autotuner's pipelined passes")
+    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always time)")
     ap.add_argument("--bed", action="store_true",
                     help="also time the out-of-core scan: the genotypes written as a PLINK 1 binary file (2-bit "
                          "rows) in the temp directory, read by the library's reader thread into pinned buffers "
@@ -118,6 +120,13 @@ class Pass:
             self.pipe = None
 
 
+def tune(clak, handle, G, b, se, block, args):
+    """Launch parameters from a pipelined pass over the first --tune-blocks blocks."""
+    nb = max(1, min(args.tune_blocks, G.shape[0] // block))
+    clak.clak_autotune_pipeline(handle, block_list(G[:nb * block], b[:, :nb * block], se[:, :nb * block], block),
+                                cache_path=args.tune_cache)
+
+
 def make_plan(clak, torch, w, block, precision, flags=0):
     prec = clak.CLAK_PREC_MIXED if precision == "mixed" else clak.CLAK_PREC_FP64
     plan = clak.Plan(w.n, w.pL, w.t, block, prec, flags)
@@ -168,10 +177,14 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=Non
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / steps
         clak.clak_plan_set_profiling(plan.handle, clak.CLAK_PROFILE_PIPELINED)
+        ev0.record()
         for _ in range(steps):
             run()
+        ev1.record()
         pipe = clak.clak_plan_get_profile(plan.handle)
         busy = clak.clak_plan_get_busy(plan.handle)
+        torch.cuda.synchronize()
+        ms_prof = ev0.elapsed_time(ev1) / steps  # the profiled passes' own step time (events add host work)
         serial_steps = max(1, min(steps, 3))
         clak.clak_plan_set_profiling(plan.handle, clak.CLAK_PROFILE_SERIAL)
         for _ in range(serial_steps):
@@ -185,6 +198,7 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=Non
         prof[k] = {"launches_per_step": n / steps,
                    "mean_launch_ms": tot / n if n else 0.0,        # in the pipeline (overlapped)
                    "busy_ms_per_step": busy[k] / steps,            # union of the launch intervals
+                   "busy_share": busy[k] / steps / ms_prof,         # of the profiled pass's wall time
                    "isolated_launch_ms": alone[k][0] / alone[k][1] if alone[k][1] else 0.0}
     return ms, prof
 
@@ -229,29 +243,35 @@ def stage_flops(stage, w, block):
     return None
 
 
-def roofline(prof, w, block, precision, workload, tuning):
+def roofline(prof, w, block, precision, workload, tuning, ms_step):
     """Roofline of the stage that keeps the GPU busiest per step.
 
     achieved = algorithmic flops of one launch x launches per step / the
-    stage's busy time per step (the union of its launch intervals in the
-    pipelined profiled pass: the time during which at least one of its
-    kernels ran, so at most the step), i.e. flops per launch / busy time per
-    launch.  Beside it: the mean launch duration in the pipeline (what a
-    rocprofv3 kernel trace of the same passes averages) and the isolated one."""
-    dom = max((k for k in prof if prof[k]["launches_per_step"] > 0), key=lambda k: prof[k]["busy_ms_per_step"])
+    stage's busy time per step.  The busy time is the stage's share of a
+    pipelined profiled pass (the union of its launch intervals over that
+    pass's wall time: the time during which at least one of its kernels ran)
+    times the unprofiled step, so it never exceeds the step.  Beside it: the
+    mean launch duration in the pipeline (what a rocprofv3 kernel trace of the
+    same passes averages) and the isolated one."""
+    dom = max((k for k in prof if prof[k]["launches_per_step"] > 0), key=lambda k: prof[k]["busy_share"])
     d = prof[dom]
     flops = stage_flops(dom, w, block)
     if flops is None:
         return None
     peak, peak_name = PEAK[precision]
-    per_launch = d["busy_ms_per_step"] / d["launches_per_step"]
+    # the stage's share of the profiled pass, applied to the unprofiled step
+    # (the profiler's events stretch the profiled pass; the share is what it
+    # measures without that bias), per launch
+    per_launch = d["busy_share"] * ms_step / d["launches_per_step"]
     achieved = flops / (per_launch * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": committed_traffic(dom, precision, workload, tuning),
             "kernel": KERNELS.get((dom, precision), (dom,))[0], "avg_launch_ms": per_launch,
             "launches_per_step": d["launches_per_step"],
-            "basis": "in-pipeline busy time: union of the kernel's launch intervals (HIP events on each launch's "
-                     "own stream) per step / launches per step",
+            "basis": "in-pipeline busy time per launch: the share of a pipelined profiled pass during which at "
+                     "least one launch of the kernel ran (union of its launch intervals, HIP events on each launch's "
+                     "own stream) x the unprofiled step time / launches per step",
+            "busy_share_of_step": d["busy_share"],
             "mean_launch_ms_in_pipeline": d["mean_launch_ms"], "isolated_launch_ms": d["isolated_launch_ms"],
             "frac_isolated": flops / (d["isolated_launch_ms"] * 1e-3) / 1e12 / peak if d["isolated_launch_ms"] else None,
             "peak_source": peak_name}
@@ -359,14 +379,14 @@ def main():
     tuning = None
     if not args.no_tune:
         t0 = time.perf_counter()
-        clak.clak_autotune(plan.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
+        tune(clak, plan.handle, G, b, se, block, args)
         setup["autotune_ms"] = (time.perf_counter() - t0) * 1e3
         tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
         log(f"[bench] tuned launch parameters {tuning}")
     ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager, pv)
     cells = m * w.t
     log(f"[bench] {ms:.3f} ms/step, {cells / ms * 1e3:.4e} cells/s; stages {prof}")
-    roof = roofline(prof, w, block, args.precision, args.workload, tuning)
+    roof = roofline(prof, w, block, args.precision, args.workload, tuning, ms)
     out = {
         "metric": "GLS cells/sec (SNP x trait) at n=1000, p=4; mixed precision vs FP64",
         "value": cells / (ms * 1e-3),
@@ -402,7 +422,7 @@ def main():
         p64.close()
         out["fp64_plain"] = {"value": cells / (ms64 * 1e-3), "ms_per_step": ms64,
                              "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in prof64.items()},
-                             "roofline": roofline(prof64, w, block, "fp64", args.workload, None)}
+                             "roofline": roofline(prof64, w, block, "fp64", args.workload, None, ms64)}
         out["mixed_over_fp64"] = ms64 / ms
         log(f"[bench] FP64 plain path: {ms64:.3f} ms/step")
 
@@ -411,9 +431,9 @@ def main():
         # comparison; the headline line above is CLAK-Eig)
         torch.cuda.empty_cache()
         pc, setup_c = make_plan(clak, torch, w, block, args.precision, clak.CLAK_CHOL)
-        if not args.no_tune:
-            clak.clak_autotune(pc.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
         bc, sc = torch.empty_like(b), torch.empty_like(se)
+        if not args.no_tune:
+            tune(clak, pc.handle, G, bc, sc, block, args)
         msc, profc = timed_steps(clak, torch, pc, G, bc, sc, block, args.steps, args.warmup, args.eager, pv)
         pc.close()
         zc = (bc.double() - b.double()).abs() / se.double()
@@ -436,7 +456,7 @@ def main():
             pb, _ = make_plan(clak, torch, w, block, args.precision,
                               clak.CLAK_STAGE_GENOTYPES if args.stage_genotypes else 0)
             if not args.no_tune:
-                clak.clak_autotune(pb.handle, G[:block], b[:, :block], se[:, :block], cache_path=args.tune_cache)
+                tune(clak, pb.handle, G, b, se, block, args)
             bb, sb = torch.empty_like(b), torch.empty_like(se)
 
             h = clak.clak_bed_open(path, w.n, m, block, args.bed_depth)
@@ -490,7 +510,7 @@ def multi_trait_record(args, clak, torch):
     plan, setup = make_plan(clak, torch, w, w.block, args.precision)
     tuning = None
     if not args.no_tune:
-        clak.clak_autotune(plan.handle, G[:w.block], b[:, :w.block], se[:, :w.block], cache_path=args.tune_cache)
+        tune(clak, plan.handle, G, b, se, w.block, args)
         tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
     ms, prof = timed_steps(clak, torch, plan, G, b, se, w.block, args.steps, args.warmup, args.eager)
     plan.close()
@@ -500,7 +520,7 @@ def multi_trait_record(args, clak, torch):
            "steps": args.steps, "warmup": args.warmup, "dtype": "i8" if args.precision == "mixed" else "f64",
            "config": {"n": w.n, "p_L": w.pL, "p": w.pL + 1, "m": w.m, "t": w.t, "block": w.block,
                       "precision": args.precision, "tuning": tuning},
-           "roofline": roofline(prof, w, w.block, args.precision, "c2", tuning),
+           "roofline": roofline(prof, w, w.block, args.precision, "c2", tuning, ms),
            "stage_busy_ms_per_step": {k: v["busy_ms_per_step"] for k, v in prof.items()},
            "setup_ms": setup}
     rec["parity_sample"] = parity_sample(w, b.cpu().numpy(), se.cpu().numpy())
@@ -513,8 +533,8 @@ def multi_trait_record(args, clak, torch):
 def run_cohorts(args, clak, torch):
     """The batched configuration: eight cohorts of uneven n and t, each a plan
     with its own kinship eigendecomposition, submitted as one clak_batch
-    launch (every cohort a block pipeline over its SNP blocks, the
-    cohorts concurrent).  A step is one launch over all cohorts."""
+    launch (rounds of one SNP block per cohort, each round one launch per
+    kernel over all cohorts).  A step is one launch over all cohorts."""
     from synth import cohort_workloads
     _, wname = WORKLOADS["c3"]
     log(f"[bench] generating workload c3: {wname}")
@@ -526,7 +546,7 @@ def run_cohorts(args, clak, torch):
         se = torch.empty_like(b)
         plan, st = make_plan(clak, torch, w, C3_BLOCK, args.precision)
         if not args.no_tune:
-            clak.clak_autotune(plan.handle, G[:C3_BLOCK], b[:, :C3_BLOCK], se[:, :C3_BLOCK], cache_path=args.tune_cache)
+            tune(clak, plan.handle, G, b, se, C3_BLOCK, args)
         for k, v in st.items():
             setup[k] = setup.get(k, 0.0) + v
         plans.append(plan)
@@ -535,6 +555,7 @@ def run_cohorts(args, clak, torch):
         log(f"[bench]   cohort n={w.n} t={w.t} m={w.m}")
     handles = [p.handle for p in plans]
     batch = clak.clak_batch_create(handles, blocks)
+    batch_info = clak.clak_batch_get_info(batch)
     try:
         for _ in range(args.warmup):
             clak.clak_batch_launch(batch)
@@ -579,7 +600,10 @@ def run_cohorts(args, clak, torch):
                      "peak_source": peak_name},
         "stage_launch_ms_summed_over_cohorts": {k: sum(p[k][0] for p in profs) / args.steps for k in profs[0]},
         "stage_busy_ms_per_cohort": [{k: v / args.steps for k, v in bz.items()} for bz in busys],
-        "launch": "clak_batch_launch: one pipeline per cohort on its own streams, cohorts concurrent",
+        "launch": ("clak_batch_launch: rounds of one block per cohort, each round one launch per kernel over all "
+                   "cohorts (costliest first), on three streams" if batch_info[0] else
+                   "clak_batch_launch: rounds of one block per cohort, per-cohort launches, on three streams"),
+        "batch": {"batched": batch_info[0], "rounds": batch_info[1], "streams": batch_info[2]},
         "setup_ms": setup,
     }
     if not args.no_cpu_baseline:

@@ -279,14 +279,25 @@ clak_status clak_pipeline_destroy(clak_pipeline_t pipe);
 
 /* Several cohorts in one submission: plans[k] (distinct plans, each READY, on
  * the same device) runs its n_blocks[k] blocks, taken consecutively from
- * `blocks`, as a pipeline on its own three streams; the cohorts run
- * concurrently, so the hardware scheduler balances cohorts of uneven n and t.
- * Same lifetime rules as a pipeline. */
+ * `blocks`.  The batch runs on three streams of its own (an ingest stream and
+ * two compute streams), whatever the number of plans, in rounds: round r
+ * takes block r of every plan that has one, ordered by the work of one of
+ * its blocks (n (2 n + 10 (p_L + 2) t) per SNP, largest first).  When the
+ * plans' kernels agree (mixed precision, several traits, the same p_L <= 3
+ * and output form, at most 16 plans) each round is one launch per kernel
+ * (ingest, rotation, digit encoding, grid contraction) whose grid holds every
+ * plan's work-groups in that order; otherwise the plans' per-block launches
+ * run in that order on the same streams.  Same lifetime rules as a pipeline. */
 clak_status clak_batch_create(clak_batch_t* batch, int n_plans, const clak_plan_t* plans, const int64_t* n_blocks,
                               const clak_block* blocks, int g_dtype, int out_dtype);
 
 /* Enqueues the batch, forked from and joined back to hip_stream (may be NULL). */
 clak_status clak_batch_launch(clak_batch_t batch, void* hip_stream);
+
+/* How the batch runs: *batched = 1 when every round is one launch per kernel
+ * over all its plans, *rounds the number of rounds, *streams the streams it
+ * uses (3).  Null outputs skipped.  Errors: CLAK_E_ARG (null batch). */
+clak_status clak_batch_get_info(clak_batch_t batch, int* batched, int64_t* rounds, int* streams);
 
 /* Waits for the batch's streams and destroys them; frees no caller memory. */
 clak_status clak_batch_destroy(clak_batch_t batch);
@@ -300,13 +311,18 @@ clak_status clak_batch_destroy(clak_batch_t batch);
  *             to 5 through registers, one slice ahead);
  *   rot_rg  : the rotation's XCD row groups (1, 2, 4, 8; the 8 XCDs split into
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
- *   grid_tt : traits per work-group of the grid contraction (32 or 64);
- *   grid_xt : XCD trait groups of the grid contraction (1, 2, 4, 8).
+ *   grid_tt : the grid contraction's kernel: 0 the one-pass kernel (p_L <= 3;
+ *             128 SNPs x 32 traits per work-group), 32 or 64 the two-stage
+ *             kernel with that many traits per work-group;
+ *   grid_xt : with grid_tt = 0, the SNP tiles of an XCD walked together over
+ *             all trait groups (1, 2, 4, 8; built-in 4); with 32 or 64, the
+ *             XCD trait groups (1, 2, 4, 8).
  * 0 selects the built-in choice: for the rotation, 64 x 256 tiles
  * (configuration 6) in single-trait plans whose blocks hold at least 8192
  * SNPs (slower per launch alone, faster in the block pipeline), with one XCD
  * row group under CLAK_CHOL and two otherwise, else 64 x 128 tiles and two
- * row groups.  Errors: CLAK_E_ARG for other values. */
+ * row groups; for the grid, the one-pass kernel for p_L <= 3.
+ * Errors: CLAK_E_ARG for other values. */
 clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
 /* The sizes and options the plan was created with (n, p_L, t, max_block,
@@ -320,19 +336,31 @@ clak_status clak_plan_get_shape(clak_plan_t plan, int64_t* n, int64_t* p_L, int6
 clak_status clak_plan_get_tuning(clak_plan_t plan, int* rot_cfg, int* rot_rg, int* grid_tt, int* grid_xt);
 
 /* clak_run_block that first picks the launch parameters for this plan and
- * block size.  With a readable cache_path holding a line for the shape
- * (device, n_pad, p_L, t, m_blk) its choice is applied; otherwise every
- * candidate of clak_plan_set_tuning is timed with HIP events on this block
- * (three launches each of the rotation, unless the plan takes the built-in
- * 64 x 256 tiles, which are chosen for the pipeline, and, with several traits,
- * of the grid kernel unless CLAK_OUT_FULL with p_L > 3), a candidate kept in
- * the plan only when more than 3 % faster than the built-in choice and, when cache_path is
- * not NULL, appended to that text file ("<shape> rot_cfg=C rot_rg=R
- * grid_tt=T grid_xt=X").  The block's outputs are then computed with the
- * chosen parameters, as by clak_run_block (without p-values).  Synchronous.  The FP64 path has nothing
- * to tune and runs the block.  Errors: as clak_run_block, CLAK_E_DEVICE. */
+ * block: clak_autotune_pipeline over this one block (timed alone, so the
+ * choice suits blocks run one at a time; pipelines should be tuned with
+ * clak_autotune_pipeline over a few of their blocks).  Without p-values.
+ * Synchronous.  Errors: as clak_run_block, CLAK_E_DEVICE. */
 clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, void* d_b,
                           void* d_se, int out_dtype, int64_t ldo, uint8_t* d_flags, const char* cache_path);
+
+/* Picks the launch parameters of clak_plan_set_tuning for this plan by timing
+ * the block pipeline (as clak_pipeline_launch runs it) over the given blocks,
+ * which should be a few (3 to 6) blocks of the size the plan will stream:
+ * each candidate gets one warm-up pass and the best of three timed passes,
+ * first every rotation configuration and XCD row grouping (with the grid at
+ * its built-in choice), then, with several traits, every grid kernel and
+ * XCD grouping (none for the full vector with p_L > 3); the built-in choice
+ * is kept unless a candidate is more than 2 % faster.  The choice stays in the
+ * plan; with cache_path (nullable) a line "<shape> rot_cfg=C rot_rg=R
+ * grid_tt=T grid_xt=X" is appended, the shape being the device architecture,
+ * n_pad, p_L, t, the first block's size, the number of blocks and the plan's
+ * flags, and a later call with a line for the same shape takes it without
+ * timing.  The blocks' outputs are computed (the last pass runs with the
+ * choice; every candidate computes the same bits).  The FP64 path has nothing
+ * to tune and runs the blocks.  Synchronous.  Errors: as
+ * clak_pipeline_create, CLAK_E_DEVICE. */
+clak_status clak_autotune_pipeline(clak_plan_t plan, int64_t n_blocks, const clak_block* blocks, int g_dtype,
+                                   int out_dtype, const char* cache_path);
 
 /* Out-of-core genotype input.  A SNP-major PLINK 1 binary genotype file (the
  * bytes 0x6c 0x1b 0x01, then m rows of (n + 3) / 4 bytes in the CLAK_G_P2

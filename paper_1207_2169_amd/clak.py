@@ -82,6 +82,8 @@ SIGNATURES.update({
     "clak_batch_create": (_I, [ctypes.POINTER(_P), _I, ctypes.POINTER(_P), ctypes.POINTER(_I64),
                                ctypes.POINTER(clak_block), _I, _I]),
     "clak_batch_launch": (_I, [_P, _P]),
+    "clak_batch_get_info": (_I, [_P, _P, _P, _P]),
+    "clak_autotune_pipeline": (_I, [_P, _I64, ctypes.POINTER(clak_block), _I, _I, ctypes.c_char_p]),
     "clak_batch_destroy": (_I, [_P]),
 })
 
@@ -443,6 +445,13 @@ def clak_pipeline_create(plan: int, blocks) -> int:
     return h.value
 
 
+def clak_autotune_pipeline(plan: int, blocks, cache_path: Optional[str] = None):
+    """Picks the launch parameters by timing the pipeline over blocks = [(G, b, se[, flags]), ...]."""
+    arr, gdt, odt = _block_array(clak_plan_get_shape(plan), blocks)
+    cp = cache_path.encode() if cache_path is not None else None
+    _check(lib().clak_autotune_pipeline(plan, len(arr), arr, gdt, odt, cp), "clak_autotune_pipeline")
+
+
 def clak_pipeline_launch(pipe: int):
     _check(lib().clak_pipeline_launch(pipe), "clak_pipeline_launch")
 
@@ -471,6 +480,14 @@ def clak_batch_create(plans, blocks_per_plan) -> int:
 def clak_batch_launch(batch: int, stream: Optional[torch.cuda.Stream] = None):
     s = stream if stream is not None else torch.cuda.current_stream()
     _check(lib().clak_batch_launch(batch, s.cuda_stream), "clak_batch_launch")
+
+
+def clak_batch_get_info(batch: int):
+    """(batched, rounds, streams) of a batch."""
+    b, r, s = ctypes.c_int(0), ctypes.c_int64(0), ctypes.c_int(0)
+    _check(lib().clak_batch_get_info(batch, ctypes.cast(ctypes.byref(b), _P), ctypes.cast(ctypes.byref(r), _P),
+                                     ctypes.cast(ctypes.byref(s), _P)), "clak_batch_get_info")
+    return bool(b.value), r.value, s.value
 
 
 def clak_batch_destroy(batch: int):

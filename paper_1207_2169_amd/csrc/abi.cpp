@@ -671,114 +671,8 @@ clak_status clak_autotune(clak_plan_t h, int64_t m_blk, const void* d_G, int g_d
   Plan* p = as_plan(h);
   clak_status s = need_state(p, ST_READY, "autotune");
   if (s) return s;
-  s = validate_block(p, m_blk, d_G, g_dtype, ldg, d_b, d_se, out_dtype, ldo, d_flags, nullptr);
-  if (s) return s;
-  const CellOut out = cell_out(d_b, d_se, nullptr, d_flags, ldo, out_dtype);
-  auto run = [&]() { return enqueue_block(p, 0, p->stream, p->stream, nullptr, m_blk, d_G, g_dtype, ldg, out); };
-  if (p->prec != CLAK_PREC_MIXED) {  // nothing to tune on the FP64 path
-    s = run();
-    return s ? s : ok();
-  }
-  const bool tune_grid = !p->fused_t1 && (p->pL <= 3 || !(p->flags & CLAK_OUT_FULL));
-  char key[160];
-  std::snprintf(key, sizeof key, "gfx950 n_pad=%lld p_L=%lld t=%lld m_blk=%lld", (long long)p->n_pad,
-                (long long)p->pL, (long long)p->t, (long long)m_blk);
-  // a cached choice for this shape
-  if (cache_path) {
-    if (FILE* f = std::fopen(cache_path, "r")) {
-      char line[320];
-      bool found = false;
-      while (!found && std::fgets(line, sizeof line, f)) {
-        const size_t kl = std::strlen(key);
-        if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
-        int cfg = 0, rg = 0, tt = 0, xt = 0;
-        if (std::sscanf(line + kl, " rot_cfg=%d rot_rg=%d grid_tt=%d grid_xt=%d", &cfg, &rg, &tt, &xt) == 4 &&
-            clak_plan_set_tuning(h, cfg, rg, tt, xt) == CLAK_OK)
-          found = true;
-      }
-      std::fclose(f);
-      if (found) {
-        s = run();
-        return s ? s : ok();
-      }
-    }
-  }
-  // measure: one full block fills slot 0, then each candidate launch of the
-  // rotation and of the grid kernel is timed on it (all candidates compute
-  // bitwise identical results; only the work-group-to-tile mapping differs)
-  s = run();
-  if (s) return s;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-    if (e0) (void)hipEventDestroy(e0);
-    return fail(CLAK_E_DEVICE, "autotune: event creation failed");
-  }
-  const int prof = p->profiling;
-  p->profiling = CLAK_PROFILE_OFF;
-  hipError_t err = hipSuccess;
-  auto time_ms = [&](auto&& launch) -> float {
-    float best = 1e30f;
-    for (int rep = 0; rep < 3 && err == hipSuccess; ++rep) {
-      err = hipEventRecord(e0, p->stream);
-      if (err == hipSuccess) err = launch();
-      if (err == hipSuccess) err = hipEventRecord(e1, p->stream);
-      if (err == hipSuccess) err = hipEventSynchronize(e1);
-      float ms = 0.0f;
-      if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-      if (err == hipSuccess && rep > 0 && ms < best) best = ms;  // the first launch warms the caches
-    }
-    return best;
-  };
-  // a candidate replaces the built-in choice only when it is more than 3 %
-  // faster on this block (timings alone, without the concurrent ingest of a
-  // pipeline, are not worth chasing smaller differences)
-  constexpr float MARGIN = 0.97f;
-  const int pow2[4] = {1, 2, 4, 8};
-  p->rot_cfg = 0;
-  p->rot_rg = 0;
-  int best_cfg = 0, best_rg = 0;
-  // the built-in wide tiles of single-trait plans are chosen for the block
-  // pipeline, where they are faster although a launch alone is slower, so
-  // launches timed alone do not replace them
-  if (!rot_wide_builtin(*p)) {
-    float best_t = MARGIN * time_ms([&] { return launch_rotate_snps(*p, m_blk); });
-    for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
-      for (int rg : pow2) {
-        p->rot_cfg = cfg;
-        p->rot_rg = rg;
-        const float ms = time_ms([&] { return launch_rotate_snps(*p, m_blk); });
-        if (ms < best_t) best_t = ms, best_cfg = cfg, best_rg = rg;
-      }
-  }
-  p->rot_cfg = best_cfg;
-  p->rot_rg = best_rg;
-  int best_tt = 0, best_xt = 0;
-  if (tune_grid) {
-    p->grid_tt = 0;
-    p->grid_xt = 0;
-    float best_t = MARGIN * time_ms([&] { return launch_grid(*p, m_blk, out); });
-    for (int tt : {32, 64})
-      for (int xt : pow2) {
-        p->grid_tt = tt;
-        p->grid_xt = xt;
-        const float ms = time_ms([&] { return launch_grid(*p, m_blk, out); });
-        if (ms < best_t) best_t = ms, best_tt = tt, best_xt = xt;
-      }
-  }
-  p->grid_tt = best_tt;
-  p->grid_xt = best_xt;
-  p->profiling = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (err != hipSuccess) return fail(CLAK_E_DEVICE, "autotune: %s", hipGetErrorString(err));
-  if (cache_path) {
-    if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s rot_cfg=%d rot_rg=%d grid_tt=%d grid_xt=%d\n", key, p->rot_cfg, p->rot_rg, p->grid_tt,
-                   p->grid_xt);
-      std::fclose(f);
-    }
-  }
-  s = run();  // the block's outputs, with the chosen parameters
+  clak_block B{m_blk, d_G, ldg, d_b, d_se, ldo, d_flags, nullptr};
+  s = autotune_blocks(p, 1, &B, g_dtype, out_dtype, cache_path, "autotune");
   return s ? s : ok();
 }
 

@@ -214,6 +214,7 @@ inline void select_slot(Plan& p, int k) {
 
 // ---- ABI helpers (abi.cpp) ----
 clak_status fail(clak_status s, const char* fmt, ...);
+hipEvent_t take_event(Plan* p);
 clak_status ok();
 clak_status need_state(const Plan* p, int min_state, const char* what);
 bool device_accessible(const Plan* p, const void* ptr);
@@ -222,9 +223,13 @@ clak_status validate_block(const Plan* p, int64_t m_blk, const void* d_G, int g_
                            const void* d_se, int out_dtype, int64_t ldo, const void* d_flags, const void* d_pval);
 clak_status enqueue_block(Plan* p, int slot, hipStream_t s_in, hipStream_t s_main, hipEvent_t ingested,
                           int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg, const CellOut& out);
+clak_status autotune_blocks(Plan* p, int64_t n_blocks, const clak_block* blocks, int g_dtype, int out_dtype,
+                            const char* cache_path, const char* what);
 clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
                           const std::function<clak_status(int64_t, clak_block*)>& get,
                           const std::function<clak_status(int64_t, hipStream_t)>& after, const char* what);
+
+constexpr int MAX_BATCH = 16;  // plans in one batched launch
 
 // One plan's block in a batched launch (several plans' blocks in one grid):
 // the plan, the workspace slot the block uses, its size, input and outputs.

@@ -125,7 +125,6 @@ __device__ __forceinline__ double g32_value(const v16i (&acc)[4], int r) {
 // [start[k], start[k + 1]) of the flattened grid (its own grid, flattened,
 // after the plans before it; every range a multiple of 8 where the kernel's
 // tile map is XCD-aware, so that a work-group's XCD is its local index mod 8).
-constexpr int MAX_BATCH = 16;
 template <class A>
 struct BatchArgs {
   int count;

@@ -343,10 +343,13 @@ hipError_t launch_grid_ring(const Plan& p, int64_t m_blk, const CellOut& out) {
   return hipGetLastError();
 }
 
+// Plans whose blocks can share batched launches.  A batched round always
+// takes the ring grid kernel and the built-in rotation tiles of multi-trait
+// plans (each plan keeps its XCD groupings); every launch variant computes
+// the same bits, so a plan's tuned variants need not match.
 bool batch_compatible(const Plan& a, const Plan& b) {
   auto ok = [](const Plan& p) {
-    return p.prec == CLAK_PREC_MIXED && !p.fused_t1 && p.pL <= 3 && p.grid_tt == 0 &&
-           !(p.flags & CLAK_STAGE_GENOTYPES);
+    return p.prec == CLAK_PREC_MIXED && !p.fused_t1 && p.pL <= 3 && !(p.flags & CLAK_STAGE_GENOTYPES);
   };
   return ok(a) && ok(b) && a.pL == b.pL && (a.flags & CLAK_OUT_FULL) == (b.flags & CLAK_OUT_FULL) &&
          a.device == b.device;
@@ -361,7 +364,7 @@ hipError_t launch_grid_batch(const BatchItem* it, int count, hipStream_t st) {
     const Workspace& W = p.ws;
     const Slot& S = W.slot[it[k].slot];
     const int64_t ns = (it[k].m_blk + 127) / 128, ng = (p.t + 31) / 32, gs = (ns + 7) / 8;
-    const int sg = p.grid_xt ? p.grid_xt : 4;
+    const int sg = (p.grid_tt == 0 && p.grid_xt) ? p.grid_xt : 4;  // grid_xt means sg only for the ring kernel
     B.a[k] = GridArgs{p.n_pad, it[k].m_blk, p.mb_pad, p.t, p.t_pad, ns, ng, sg, S.Xd, W.Vd, W.Dd, W.vs, W.ds, W.tpar,
                       S.sstat, p.flags, it[k].out};
     B.start[k + 1] = B.start[k] + 8 * gs * ng;

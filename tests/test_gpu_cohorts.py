@@ -2,7 +2,8 @@
 n = 500 .. 4000 individuals, each with its own kinship (from 2 n genotype
 columns) and covariates, t between 10 and 2000 traits (log-uniform), 5 10^4
 SNPs each in blocks of 10^4, submitted as one clak_batch launch (the SNP
-blocks of section 3 streamed for every cohort in one submission).  Every
+blocks of section 3 streamed for every cohort in one submission): five rounds,
+each one launch per kernel over all eight cohorts, on three streams.  Every
 cohort is checked against the oracle on a stratified sample: six traits (the
 first, the last and four random ones) x 200 SNPs (block edges and random
 ones), 1200 cells per cohort; every cell of every cohort must be finite and
@@ -44,6 +45,8 @@ def test_batched_cohorts_against_the_oracle():
                            for s in range(0, w.m, BLOCK)])
         batch = clak.clak_batch_create([p.handle for p in plans], blocks)
         try:
+            batched, rounds, streams = clak.clak_batch_get_info(batch)
+            assert batched and rounds == 5 and streams == 3  # one launch per kernel and round, three streams
             clak.clak_batch_launch(batch)
             torch.cuda.synchronize()
         finally:
