@@ -58,8 +58,14 @@ def parse():
     ap.add_argument("--no-tune", action="store_true",
                     help="skip clak_autotune_pipeline (launch parameters timed on a pipelined pass over the first "
                          "blocks before the timed region)")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch parameters instead of the autotuner, as rot_cfg:C,rot_rg:R,grid_tt:T,grid_xt:X "
+                         "(0: built-in; a profile of a tuned run repeats its choice this way)")
     ap.add_argument("--tune-blocks", type=int, default=4, help="blocks of the autotuner's pipelined passes")
-    ap.add_argument("--tune-cache", default=None, help="autotuner cache file (default: none, always time)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file, read and appended to (default: a temporary copy of the library's "
+                         "tuning database for gfx950, so shapes it lists are not timed again)")
+    ap.add_argument("--retune", action="store_true", help="time every shape, ignoring the tuning database")
     ap.add_argument("--bed", action="store_true",
                     help="also time the out-of-core scan: the genotypes written as a PLINK 1 binary file (2-bit "
                          "rows) in the temp directory, read by the library's reader thread into pinned buffers "
@@ -120,11 +126,42 @@ class Pass:
             self.pipe = None
 
 
+TUNING_DB = os.path.join(ROOT, "paper_1207_2169_amd", "tuning", "gfx950.txt")
+
+
+def tune_cache_path(args):
+    """The cache file the autotuner reads and appends to: --tune-cache, else a
+    temporary copy of the library's tuning database (lines written by
+    clak_autotune_pipeline on an MI355X), or none with --retune."""
+    if args.tune_cache or args.retune:
+        return args.tune_cache
+    import shutil
+    import tempfile
+    fd, path = tempfile.mkstemp(prefix="clak_tuning_", suffix=".txt")
+    os.close(fd)
+    if os.path.exists(TUNING_DB):
+        shutil.copyfile(TUNING_DB, path)
+    import atexit
+    atexit.register(os.remove, path)
+    args.tune_cache = path
+    return path
+
+
 def tune(clak, handle, G, b, se, block, args):
-    """Launch parameters from a pipelined pass over the first --tune-blocks blocks."""
+    """Launch parameters for the plan: the fixed ones of --tuning, else
+    clak_autotune_pipeline over the first --tune-blocks blocks (a pipelined
+    pass per candidate), which takes them from the cache file when it lists
+    the shape.  Returns "fixed", "database" or "timed"."""
+    if args.tuning:
+        clak.clak_plan_set_tuning(handle, *tuning_tuple(dict(p.split(":") for p in args.tuning.split(","))))
+        return "fixed"
+    path = tune_cache_path(args)
+    size = os.path.getsize(path) if path and os.path.exists(path) else -1
     nb = max(1, min(args.tune_blocks, G.shape[0] // block))
     clak.clak_autotune_pipeline(handle, block_list(G[:nb * block], b[:, :nb * block], se[:, :nb * block], block),
-                                cache_path=args.tune_cache)
+                                cache_path=path)
+    grew = path is None or not os.path.exists(path) or os.path.getsize(path) != size
+    return "timed" if grew else "database"
 
 
 def make_plan(clak, torch, w, block, precision, flags=0):
@@ -203,30 +240,50 @@ def timed_steps(clak, torch, plan, G, b, se, block, steps, warmup, eager, pv=Non
     return ms, prof
 
 
-KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): ("k_grid32", "k_mixed.hip"),
+KERNELS = {("rotate", "mixed"): ("k_rot_i8", "k_mixed.hip"), ("grid", "mixed"): ("k_grid_ring", "k_grid.hip"),
            ("rotate", "fp64"): ("k_rot64", "k_fp64.hip"), ("grid", "fp64"): ("k_grid64", "k_fp64.hip")}
 
 
-def committed_traffic(stage, precision, workload, tuning):
+def stage_kernel(stage, precision, pL, tuning):
+    """(kernel name, source file) of a stage's launches: the mixed grid runs
+    the one-pass ring kernel for p_L <= 3 unless the tuner picked a two-stage
+    tile (grid_tt 32 or 64), which runs k_grid32."""
+    if stage == "grid" and precision == "mixed" and (pL > 3 or (tuning and tuning.get("grid_tt"))):
+        return ("k_grid32", "k_mixed.hip")
+    return KERNELS.get((stage, precision))
+
+
+TUNING_KEYS = ("rot_cfg", "rot_rg", "grid_tt", "grid_xt")
+
+
+def tuning_tuple(tuning):
+    """The four launch parameters (0: built-in) of a tuning dict, or of None."""
+    return tuple(int((tuning or {}).get(k, 0)) for k in TUNING_KEYS)
+
+
+def committed_traffic(stage, precision, pL, workload, tuning):
     """HBM bytes per launch of the stage's kernel from the committed rocprofv3
     summaries (FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy), or None when
-    none matches the current kernel source, or when the summary was taken with
-    the built-in launch parameters and this run's tuner chose others."""
+    none was taken from the current kernel source with this run's launch
+    parameters (a line "tuning=builtin" stands for all four at 0)."""
     import glob
     import hashlib
-    key = KERNELS.get((stage, precision))
+    key = stage_kernel(stage, precision, pL, tuning)
     if key is None:
         return None
     kernel, src = key
     sha = hashlib.sha256(open(os.path.join(ROOT, "paper_1207_2169_amd", "csrc", src), "rb").read()).hexdigest()[:16]
+    want = tuning_tuple(tuning)
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for line in open(path):
             if "traffic_bytes_per_launch=" not in line:
                 continue
             kv = dict(tok.split("=", 1) for tok in line.split() if "=" in tok)
-            if kv.get("workload") == workload and kv.get("kernel") == kernel and kv.get("sha256_16") == sha:
-                if kv.get("tuning") == "builtin" and tuning and any(tuning.values()):
-                    return None
+            if kv.get("workload") != workload or kv.get("kernel") != kernel or kv.get("sha256_16") != sha:
+                continue
+            tv = kv.get("tuning", "builtin")
+            got = (0, 0, 0, 0) if tv == "builtin" else tuning_tuple(dict(p.split(":") for p in tv.split(",")))
+            if got == want:
                 return float(kv["traffic_bytes_per_launch"])
     return None
 
@@ -265,8 +322,8 @@ def roofline(prof, w, block, precision, workload, tuning, ms_step):
     per_launch = d["busy_share"] * ms_step / d["launches_per_step"]
     achieved = flops / (per_launch * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": committed_traffic(dom, precision, workload, tuning),
-            "kernel": KERNELS.get((dom, precision), (dom,))[0], "avg_launch_ms": per_launch,
+            "traffic": committed_traffic(dom, precision, w.pL, workload, tuning),
+            "kernel": (stage_kernel(dom, precision, w.pL, tuning) or (dom,))[0], "avg_launch_ms": per_launch,
             "launches_per_step": d["launches_per_step"],
             "basis": "in-pipeline busy time per launch: the share of a pipelined profiled pass during which at "
                      "least one launch of the kernel ran (union of its launch intervals, HIP events on each launch's "
@@ -379,9 +436,9 @@ def main():
     tuning = None
     if not args.no_tune:
         t0 = time.perf_counter()
-        tune(clak, plan.handle, G, b, se, block, args)
+        source = tune(clak, plan.handle, G, b, se, block, args)
         setup["autotune_ms"] = (time.perf_counter() - t0) * 1e3
-        tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
+        tuning = dict(zip(TUNING_KEYS, clak.clak_plan_get_tuning(plan.handle)), source=source)
         log(f"[bench] tuned launch parameters {tuning}")
     ms, prof = timed_steps(clak, torch, plan, G, b, se, block, args.steps, args.warmup, args.eager, pv)
     cells = m * w.t
@@ -510,8 +567,8 @@ def multi_trait_record(args, clak, torch):
     plan, setup = make_plan(clak, torch, w, w.block, args.precision)
     tuning = None
     if not args.no_tune:
-        tune(clak, plan.handle, G, b, se, w.block, args)
-        tuning = dict(zip(("rot_cfg", "rot_rg", "grid_tt", "grid_xt"), clak.clak_plan_get_tuning(plan.handle)))
+        source = tune(clak, plan.handle, G, b, se, w.block, args)
+        tuning = dict(zip(TUNING_KEYS, clak.clak_plan_get_tuning(plan.handle)), source=source)
     ms, prof = timed_steps(clak, torch, plan, G, b, se, w.block, args.steps, args.warmup, args.eager)
     plan.close()
     cells = w.m * w.t

@@ -346,11 +346,15 @@ clak_status clak_autotune(clak_plan_t plan, int64_t m_blk, const void* d_G, int 
 /* Picks the launch parameters of clak_plan_set_tuning for this plan by timing
  * the block pipeline (as clak_pipeline_launch runs it) over the given blocks,
  * which should be a few (3 to 6) blocks of the size the plan will stream:
- * each candidate gets one warm-up pass and the best of three timed passes,
  * first every rotation configuration and XCD row grouping (with the grid at
  * its built-in choice), then, with several traits, every grid kernel and
- * XCD grouping (none for the full vector with p_L > 3); the built-in choice
- * is kept unless a candidate is more than 2 % faster.  The choice stays in the
+ * XCD grouping (none for the full vector with p_L > 3).  Each candidate gets
+ * one warm-up pass and the best of three timed passes; the built-in choice and
+ * the three fastest others are then timed again in three interleaved rounds.
+ * The fastest of these is taken if it is more than 2 % faster than the
+ * built-in choice, in favour of the first candidate (in the order above)
+ * within 1 % of it, so that near-equal candidates do not alternate from run
+ * to run.  The choice stays in the
  * plan; with cache_path (nullable) a line "<shape> rot_cfg=C rot_rg=R
  * grid_tt=T grid_xt=X" is appended, the shape being the device architecture,
  * n_pad, p_L, t, the first block's size, the number of blocks and the plan's

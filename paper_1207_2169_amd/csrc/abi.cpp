@@ -220,6 +220,22 @@ size_t workspace_bytes(const Plan& p, Workspace* w, char* base) {
   return off;
 }
 
+// The plan's sizes and derived paddings (no device call).
+void init_shape(Plan& p, int64_t n, int64_t p_L, int64_t t, int64_t max_block, int precision, uint32_t flags) {
+  p.n = n;
+  p.pL = p_L;
+  p.t = t;
+  p.max_block = max_block;
+  p.prec = precision;
+  p.flags = flags;
+  p.n_pad = roundup(n, KPAD);
+  p.mb_pad = roundup(max_block, SNP_PAD);
+  p.t_pad = roundup(t, TRAIT_PAD);
+  p.fused_t1 = (t == 1);
+  p.zlin = (lin_rows(p) && n + p_L + 1 <= p.n_pad) ? n : p.n_pad;
+  p.zrows = p.n_pad + ((lin_rows(p) && p.zlin == p.n_pad) ? ZEXT : 0);
+}
+
 }  // namespace clak
 
 extern "C" {
@@ -249,18 +265,7 @@ clak_status clak_plan_create(clak_plan_t* out, int64_t n, int64_t p_L, int64_t t
     return fail(CLAK_E_UNSUPPORTED, "plan_create: size too large");
   Plan* p = new (std::nothrow) Plan();
   if (!p) return fail(CLAK_E_DEVICE, "plan_create: out of host memory");
-  p->n = n;
-  p->pL = p_L;
-  p->t = t;
-  p->max_block = max_block;
-  p->prec = precision;
-  p->flags = flags;
-  p->n_pad = roundup(n, KPAD);
-  p->mb_pad = roundup(max_block, SNP_PAD);
-  p->t_pad = roundup(t, TRAIT_PAD);
-  p->fused_t1 = (t == 1);
-  p->zlin = (lin_rows(*p) && n + p_L + 1 <= p->n_pad) ? n : p->n_pad;
-  p->zrows = p->n_pad + ((lin_rows(*p) && p->zlin == p->n_pad) ? ZEXT : 0);
+  init_shape(*p, n, p_L, t, max_block, precision, flags);
   if (hipGetDevice(&p->device) != hipSuccess) {
     delete p;
     return fail(CLAK_E_DEVICE, "plan_create: no HIP device");

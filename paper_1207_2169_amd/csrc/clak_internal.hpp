@@ -170,6 +170,7 @@ struct Plan {
   int* hstat = nullptr;     // pinned host mirror of dstat
 };
 
+void init_shape(Plan& p, int64_t n, int64_t p_L, int64_t t, int64_t max_block, int precision, uint32_t flags);
 size_t workspace_bytes(const Plan& p, Workspace* carve, char* base);
 size_t slot_bytes(const Plan& p, Slot* carve, char* base);
 

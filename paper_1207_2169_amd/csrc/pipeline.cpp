@@ -270,10 +270,8 @@ clak_status stream_blocks(Plan* p, int64_t n_blocks, int g_dtype, int out_dtype,
 // over the caller's blocks (all on the plan's stream through the pipeline's
 // streams, as clak_pipeline_launch runs them) for each candidate: the
 // rotation's tile configuration and XCD row groups first (with the grid at
-// its built-in choice), then the grid kernel and its XCD grouping.  Each
-// candidate gets one warm-up pass and the best of three timed passes; the
-// built-in choice is kept unless a candidate is more than 2 % faster.  Every
-// candidate computes the same bits, so the caller's outputs hold the result
+// its built-in choice), then the grid kernel and its XCD grouping (the
+// selection rule is at `choose` below).  Every candidate computes the same bits, so the caller's outputs hold the result
 // whichever is chosen (the last pass runs with the choice).  A cache file
 // line per shape (device architecture, n_pad, p_L, t, block size, number of
 // blocks, flags) replaces the timing when present.
@@ -342,38 +340,57 @@ clak_status autotune_blocks(Plan* p, int64_t n_blocks, const clak_block* blocks,
     }
     return best;
   };
-  constexpr float MARGIN = 0.98f;
+  // One family of candidates (candidate 0 is the built-in choice): every
+  // candidate is timed once, then the built-in one and the three fastest
+  // others again in three interleaved rounds, each keeping its best time.  The
+  // fastest finalist wins only if it beats the built-in choice by MARGIN; of
+  // the finalists within TIE of the winner the first in candidate order is
+  // taken, so that near-equal candidates do not trade places from run to run.
+  constexpr float MARGIN = 0.98f, TIE = 1.01f;
+  auto choose = [&](const std::vector<std::pair<int, int>>& cand, auto set) -> std::pair<int, int> {
+    std::vector<float> ms(cand.size(), 1e30f);
+    for (size_t c = 0; c < cand.size() && !err; ++c) {
+      set(cand[c]);
+      ms[c] = measure();
+    }
+    std::vector<size_t> order(cand.size());
+    for (size_t c = 0; c < order.size(); ++c) order[c] = c;
+    std::stable_sort(order.begin() + 1, order.end(), [&](size_t a, size_t b) { return ms[a] < ms[b]; });
+    order.resize(std::min<size_t>(order.size(), 4));
+    for (int round = 0; round < 3 && !err; ++round)
+      for (size_t c : order) {
+        set(cand[c]);
+        ms[c] = std::min(ms[c], measure());
+      }
+    size_t win = 0;
+    for (size_t c : order)
+      if (ms[c] < ms[win]) win = c;
+    if (!(ms[win] < MARGIN * ms[0])) return cand[0];
+    size_t pick = win;
+    for (size_t c : order)
+      if (c < pick && ms[c] <= TIE * ms[win] && ms[c] < MARGIN * ms[0]) pick = c;
+    return cand[pick];
+  };
   const int pow2[4] = {1, 2, 4, 8};
   p->rot_cfg = p->rot_rg = p->grid_tt = p->grid_xt = 0;
   // rotation: tile configuration x XCD row groups
-  float base = measure(), best_t = MARGIN * base;
-  int best_cfg = 0, best_rg = 0;
-  for (int cfg = 0; cfg < ROT_CONFIGS && !err; ++cfg)
-    for (int rg : pow2) {
-      p->rot_cfg = cfg;
-      p->rot_rg = rg;
-      const float ms = measure();
-      if (ms < best_t) best_t = ms, best_cfg = cfg, best_rg = rg;
-    }
-  p->rot_cfg = best_cfg;
-  p->rot_rg = best_rg;
+  std::vector<std::pair<int, int>> cand = {{0, 0}};
+  for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
+    for (int rg : pow2) cand.push_back({cfg, rg});
+  const auto rot = choose(cand, [&](std::pair<int, int> c) { p->rot_cfg = c.first, p->rot_rg = c.second; });
+  p->rot_cfg = rot.first;
+  p->rot_rg = rot.second;
   // grid (several traits): the ring kernel's XCD grouping, the two-stage
   // kernel's trait tile and XCD trait groups (no variants for the full
   // vector with p_L > 3)
   if (!p->fused_t1 && (p->pL <= 3 || !(p->flags & CLAK_OUT_FULL)) && !err) {
-    base = measure();
-    best_t = MARGIN * base;
-    int best_tt = 0, best_xt = 0;
+    cand.assign(1, {0, 0});
     for (int tt : {0, 32, 64})
-      for (int xt : pow2) {
-        if (tt == 0 && p->pL > 3) continue;  // the ring kernel takes p_L <= 3
-        p->grid_tt = tt;
-        p->grid_xt = xt;
-        const float ms = measure();
-        if (ms < best_t) best_t = ms, best_tt = tt, best_xt = xt;
-      }
-    p->grid_tt = best_tt;
-    p->grid_xt = best_xt;
+      for (int xt : pow2)
+        if (tt != 0 || p->pL <= 3) cand.push_back({tt, xt});  // the ring kernel takes p_L <= 3
+    const auto grid = choose(cand, [&](std::pair<int, int> c) { p->grid_tt = c.first, p->grid_xt = c.second; });
+    p->grid_tt = grid.first;
+    p->grid_xt = grid.second;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
