@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libclak.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["abi.cpp", "pipeline.cpp", "k_setup.hip", "k_ingest.hip", "k_fp64.hip", "k_mixed.hip", "k_grid.hip", "k_vc.hip", "k_chol.hip", "noalloc.hip", "bed.cpp"]
+SOURCES = ["abi.cpp", "pipeline.cpp", "k_setup.hip", "k_ingest.hip", "k_fp64.hip", "k_mixed.hip", "k_rotz.hip", "k_grid.hip", "k_vc.hip", "k_chol.hip", "noalloc.hip", "bed.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall", "-Wno-unused-parameter",

@@ -20,7 +20,7 @@ namespace clak {
 constexpr int64_t KPAD = 128;
 constexpr int64_t SNP_PAD = 256;  // multiple of every SNP tile width
 constexpr int64_t TRAIT_PAD = 128;
-constexpr int ROT_CONFIGS = 10;  // tile configurations of the mixed rotation (tunable)
+constexpr int ROT_CONFIGS = 11;  // tile configurations of the mixed rotation (tunable)
 constexpr int MAX_PL = 16;
 constexpr int ING_MAX_SPLITS = 8;  // individual windows of the ingest are split over at most this many work-groups
 // int8 digit encoding: a value v with |v| <= s is stored as
@@ -202,6 +202,13 @@ inline bool rot_wide_builtin(const Plan& p) { return lin_rows(p) && p.mb_pad >= 
 // operand with the wide tiles (4.01 against 4.26 ms per 10^6 SNPs), else 2.
 inline int rot_rg_builtin(const Plan& p) { return (rot_wide_builtin(p) && (p.flags & CLAK_CHOL)) ? 1 : 2; }
 
+// Rotation configuration 10, the Z-resident kernel (k_rotz.hip): mixed
+// precision, n_pad <= 1024, plain operand, p_L <= 4.  Where it does not apply
+// the configuration runs the built-in tiles.  Its single-trait partials are
+// per 32-row slice, added in pairs by the finish.
+bool rot_zs_applicable(const Plan& p);
+inline bool rot_zs_active(const Plan& p) { return p.rot_cfg == 10 && rot_zs_applicable(p); }
+
 // Points the per-block buffers of the workspace at slot k.
 inline void select_slot(Plan& p, int k) {
   const Slot& s = p.ws.slot[k];
@@ -270,6 +277,7 @@ hipError_t launch_chol_fix(const Plan& p);
 // per block
 hipError_t launch_ingest(const Plan& p, int64_t m_blk, const void* d_G, int g_dtype, int64_t ldg);
 hipError_t launch_rotate_snps(const Plan& p, int64_t m_blk);
+hipError_t launch_rotate_zs(const Plan& p, int64_t m_blk);
 hipError_t launch_encode(const Plan& p, int64_t m_blk);
 hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out);
 hipError_t launch_grid(const Plan& p, int64_t m_blk, const CellOut& out);

@@ -477,18 +477,22 @@ __global__ void __launch_bounds__(64 * WR * WC, (rot_waves<PL, EPI, CT>())) k_ro
 //   7: 1, 2, 2, DL3 as 4, direct loads
 //   8: 2, 2, 4, DL4 as 6, three slices in flight
 //   9: 2, 2, 2, DL4 as 0, three slices in flight (one work-group per CU)
+//  10: the Z-resident kernel (k_rotz.hip), where it applies
 constexpr int ROT_BM = 64;
-static_assert(ROT_CONFIGS == 10, "rotation configurations");
+static_assert(ROT_CONFIGS == 11, "rotation configurations");
 static_assert(SNP_PAD % 256 == 0 && KPAD % ROT_BM == 0 && ZEXT == ROT_BM, "rotation tiles must divide the paddings");
 
 // Single-trait finish: sums the per-row-tile partials of each SNP in a fixed
 // order and solves the cell (Schur complement, FP64).  A work-group takes 64
 // SNPs; its four waves sum interleaved row tiles, then wave 0 adds the four.
+// With pair (the Z-resident rotation) the partials are per 32-row slice and a
+// 64-row tile's partial is the sum of its two slices', first slice first, as
+// the staged rotations form it.
 // LIN 0 (FP64 path): each partial holds c', r' and a.  LIN 1 (mixed path):
 // each partial holds a; c' and r' are in the SNP's statistics (written by the
 // rotation's extra row tile).
 template <int PL, int LIN>
-__global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp,
+__global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int64_t mbp, int pair,
                                                 const double* __restrict__ part, const double* __restrict__ tpar,
                                                 const double* __restrict__ sstat, uint32_t flags, CellOut out) {
   constexpr int NP = LIN ? 1 : PL + 2;  // partial values per row tile
@@ -498,11 +502,15 @@ __global__ void __launch_bounds__(256) k_fin_t1(int64_t nrt, int64_t m_blk, int6
   double s[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) s[q] = 0.0;
-  if (i < m_blk)
-    for (int64_t rt = wid; rt < nrt; rt += 4) {
+  if (i < m_blk) {
+    if (LIN && pair)
+      for (int64_t rt = wid; rt < nrt; rt += 4) s[0] += part[(2 * rt) * mbp + i] + part[(2 * rt + 1) * mbp + i];
+    else
+      for (int64_t rt = wid; rt < nrt; rt += 4) {
 #pragma unroll
-      for (int q = 0; q < NP; ++q) s[q] += part[(rt * NP + q) * mbp + i];
-    }
+        for (int q = 0; q < NP; ++q) s[q] += part[(rt * NP + q) * mbp + i];
+      }
+  }
 #pragma unroll
   for (int q = 0; q < NP; ++q) red[wid][lane][q] = s[q];
   __syncthreads();
@@ -624,7 +632,8 @@ static hipError_t rotate_cfg(const Plan& p, int64_t m_blk) {
 }
 
 hipError_t launch_rotate_snps_mixed(const Plan& p, int64_t m_blk) {
-  switch (p.rot_cfg ? p.rot_cfg : (rot_wide_builtin(p) ? 6 : 0)) {
+  if (rot_zs_active(p)) return launch_rotate_zs(p, m_blk);
+  switch (p.rot_cfg && p.rot_cfg != 10 ? p.rot_cfg : (rot_wide_builtin(p) ? 6 : 0)) {
     case 1:
       return rotate_cfg<4, 2, 1, 0>(p, m_blk);
     case 2:
@@ -1028,12 +1037,15 @@ hipError_t launch_fin_t1(const Plan& p, int64_t m_blk, const CellOut& out) {
   const Workspace& W = p.ws;
   dim3 fgrid((unsigned)((m_blk + 63) / 64));
   const int64_t nrt = p.prec == CLAK_PREC_MIXED ? p.n_pad / ROT_BM : p.n_pad / 64;
+  const int pair = rot_zs_active(p) ? 1 : 0;
 #define CLAK_F1(PLV)                                                                                            \
   case PLV:                                                                                                     \
     if (lin_rows(p))                                                                                            \
-      k_fin_t1<PLV, 1><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
+      k_fin_t1<PLV, 1><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, pair, W.part, W.tpar, W.sstat, p.flags, \
+                                                    out);                                                       \
     else                                                                                                        \
-      k_fin_t1<PLV, 0><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, W.part, W.tpar, W.sstat, p.flags, out); \
+      k_fin_t1<PLV, 0><<<fgrid, 256, 0, p.stream>>>(nrt, m_blk, p.mb_pad, 0, W.part, W.tpar, W.sstat, p.flags,    \
+                                                    out);                                                       \
     break;
   switch (p.pL) {
     CLAK_F1(1) CLAK_F1(2) CLAK_F1(3) CLAK_F1(4) CLAK_F1(5) CLAK_F1(6) CLAK_F1(7) CLAK_F1(8)

@@ -376,7 +376,8 @@ clak_status autotune_blocks(Plan* p, int64_t n_blocks, const clak_block* blocks,
   // rotation: tile configuration x XCD row groups
   std::vector<std::pair<int, int>> cand = {{0, 0}};
   for (int cfg = 0; cfg < ROT_CONFIGS; ++cfg)
-    for (int rg : pow2) cand.push_back({cfg, rg});
+    for (int rg : pow2)
+      if (cfg != 10 || rg == 1) cand.push_back({cfg, rg});  // the Z-resident kernel has its own XCD map
   const auto rot = choose(cand, [&](std::pair<int, int> c) { p->rot_cfg = c.first, p->rot_rg = c.second; });
   p->rot_cfg = rot.first;
   p->rot_rg = rot.second;

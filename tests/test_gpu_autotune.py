@@ -45,7 +45,7 @@ def test_every_tuning_is_bitwise_identical(t, n, chol, config):
         clak.clak_run_block(plan.handle, G, *ref)
         torch.cuda.synchronize()
         assert bool(torch.isfinite(ref[0]).all()) and bool((ref[2] == 0).all())
-        for cfg in range(10):
+        for cfg in range(11):
             for rg in (1, 2, 4, 8):
                 for tt in ((0, 32, 64) if t > 1 else (0,)):
                     for xt in ((1, 2, 4, 8) if t > 1 else (0,)):
@@ -75,7 +75,7 @@ def test_autotune_matches_run_block_and_uses_cache(tmp_path):
             assert torch.equal(a, r)
         tuned = clak.clak_plan_get_tuning(plan.handle)
         # 0 keeps the built-in choice (no candidate more than 2 % faster)
-        assert tuned[0] in range(10) and tuned[1] in (0, 1, 2, 4, 8) and tuned[2] in (0, 32, 64)
+        assert tuned[0] in range(11) and tuned[1] in (0, 1, 2, 4, 8) and tuned[2] in (0, 32, 64)
         assert tuned[3] in (0, 1, 2, 4, 8)
         lines = cache.read_text().splitlines()
         assert len(lines) == 1 and lines[0].startswith("gfx950")
@@ -155,7 +155,7 @@ def test_wide_default_rotation_is_bitwise_identical(n, config, chol):
     with _plan(w, block, clak.CLAK_CHOL if chol else 0) as plan:
         ref = run(plan)
         assert bool(torch.isfinite(ref[0]).all()) and bool((ref[2] == 0).all())
-        for cfg in (5, 9, 7):
+        for cfg in (5, 9, 7, 10):
             clak.clak_plan_set_tuning(plan.handle, cfg, 2, 0, 0)
             out = run(plan)
             for a, r in zip(out, ref):

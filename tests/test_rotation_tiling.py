@@ -91,3 +91,68 @@ def test_single_trait_rows_placement(n, pL):
     assert zlin >= n and zlin + pL + 1 <= nz and nz % ROT_BM == 0
     # padding rows are used exactly when they can hold them
     assert (nz == np_) == (n + pL + 1 <= np_)
+
+
+# Z-resident rotation (configuration 10, k_rotz.hip): n_pad <= 1024, plain operand
+ZR_KS, ZR_D, ZR_WAVES = 32, 4, 8
+
+
+def zs_decompose(n, pL, m_blk, max_block, single):
+    """Per (work-group, wave, item, tile): the slice, the tile (clamped as the
+    kernel clamps it), and whether its results are kept; the kernel's launch
+    grid and index arithmetic restated."""
+    np_, nz, zlin = rows_of(n, pL, single)
+    mbp = rnd(max_block, SNP_PAD)
+    S = nz // 32
+    q = 1 if S >= 32 else (32 + S // 2) // S
+    ntl = rnd(m_blk, SNP_PAD) // 32
+    out = []
+    for bid in range(8 * S * q):
+        xcd, idx = bid % 8, bid // 8
+        s, j = idx % S, idx // S
+        T8 = (ntl + 7) // 8
+        xb = xcd * T8
+        xe = min(ntl, xb + T8)
+        Tq = (T8 + q - 1) // q
+        tb = xb + j * Tq
+        te = min(xe, tb + Tq)
+        if j >= q or tb >= te:
+            continue
+        P = (te - tb + 1) // 2
+        for w in range(ZR_WAVES):
+            NI = (P - w + ZR_WAVES - 1) // ZR_WAVES if P > w else 0
+            for i in range(NI):
+                for ct in range(2):
+                    t = tb + 2 * (w + ZR_WAVES * i) + ct
+                    out.append((s, min(t, te - 1), t < te, i, NI, w))
+    return dict(np=np_, nz=nz, mbp=mbp, S=S, ntl=ntl, items=out)
+
+
+@pytest.mark.parametrize("n,pL,m_blk,max_block", [s for s in SHAPES if rnd(s[0], KPAD) <= 32 * ZR_KS])
+def test_z_resident_rotation_map_and_addresses(n, pL, m_blk, max_block):
+    for single in (False, True):
+        d = zs_decompose(n, pL, m_blk, max_block, single)
+        np_, nz, mbp = d["np"], d["nz"], d["mbp"]
+        KS = np_ // 32
+        assert KS % ZR_D == 0 and KS >= ZR_D and KS <= ZR_KS
+        items = d["items"]
+        kept = [(s, t) for s, t, k, *_ in items if k]
+        # every (slice, 32-SNP tile) of the block exactly once
+        assert len(kept) == d["S"] * d["ntl"] and len(set(kept)) == len(kept)
+        # fragment sources: every K step of every item, the prefetch clamped
+        # to the wave's last item and step
+        loff_max = 32 * 31 + 16
+        zplane = nz * np_
+        for s, t, _, i, NI, w in items:
+            assert 0 <= t < mbp // 32
+            b_last = ((KS - 1) * mbp + 32 * t) * 32 + loff_max + 16
+            assert b_last <= mbp * np_
+            a_last = 3 * zplane + (KS - 1) * nz * 32 + 32 * s * 32 + loff_max + 16
+            assert a_last <= 4 * zplane
+            # outputs: x~ rows (EPI 0), the slice partial (EPI 1), the SNP's statistics
+            col = 32 * t + 31
+            assert col * np_ + 32 * s + 28 + 4 <= mbp * np_ or single
+            assert s * mbp + col < (np_ // 64) * mbp * (pL + 2)
+            assert col < mbp
+        # the prefetch pointer starts D steps in and never passes the wave's last (item, step)
+        assert (ZR_D // KS, ZR_D % KS) in ((0, ZR_D), (1, 0))
