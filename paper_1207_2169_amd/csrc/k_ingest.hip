@@ -141,132 +141,6 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest(IngArgs a) {
   ingest_tile<PL, ALIGN, KIND>(a, blockIdx.x, blockIdx.y);
 }
 
-// The slim variant: four waves and at most 64 registers per lane, so that a
-// work-group fits on a CU beside a work-group of the Z-resident rotation (two
-// waves of 224 registers per SIMD, 130 KB of LDS) and runs under it.  Wave w
-// takes the window parts w and w + 4 in turn; a part's sums live in the LDS
-// slots the eight-wave kernel reduces from and are formed with the same
-// additions in the same order, so the statistics are bitwise the same.
-template <int PL, int ALIGN, int KIND>
-__device__ __forceinline__ void ingest_tile_slim(const IngArgs& ia, int64_t bx, int64_t s0) {
-  const int64_t n = ia.n, np = ia.np, m_blk = ia.m_blk, m_pad = ia.m_pad, mbp = ia.mbp, ldg = ia.ldg;
-  const void* __restrict__ G = ia.G;
-  const double* __restrict__ QL = ia.QL;
-  int8_t* __restrict__ Gp = ia.Gp;
-  double* __restrict__ ipart = ia.ipart;
-  constexpr int NV = PL + 2;  // v, gg, bad
-  constexpr int WIN = 16 * ING_WAVES, NW = 4;
-  __shared__ double red[ING_WAVES][64][NV + 1];
-  __shared__ __attribute__((aligned(16))) double qs[PL][WIN];
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int64_t snp = bx * 64 + lane;
-  const int64_t S = ia.S;
-  for (int part = wid; part < ING_WAVES; part += NW)
-    for (int q = 0; q < NV; ++q) red[part][lane][q] = 0.0;
-  int bad = 0;
-  for (int64_t w0 = s0 * WIN; w0 < np; w0 += S * WIN) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < PL * WIN; e += 64 * NW) qs[e / WIN][e % WIN] = QL[w0 + e % WIN + (e / WIN) * np];
-    __syncthreads();
-#pragma unroll 1
-    for (int part = wid; part < ING_WAVES; part += NW) {
-      const int64_t i0 = w0 + 16 * part;
-      uint8_t by[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) by[e] = 0;
-      if (snp < m_blk) {
-        if (KIND == 2) {
-          const uint8_t* row = (const uint8_t*)G + snp * ldg + i0 / 4;
-          uint32_t word = 0;
-          if (i0 + 16 <= n && ALIGN >= 4) {
-            word = *(const uint32_t*)__builtin_assume_aligned(row, 4);
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (i0 + 4 * e < n) word |= (uint32_t)row[e] << (8 * e);
-          }
-#pragma unroll
-          for (int e = 0; e < 16; ++e) by[e] = (i0 + e < n) ? p2_value((word >> (2 * e)) & 3u) : 0;
-        } else if (KIND == 1) {
-          const __half* row = (const __half*)G + snp * ldg + i0;
-#pragma unroll
-          for (int e = 0; e < 16; ++e)
-            if (i0 + e < n) {
-              const float f = __half2float(row[e]);
-              by[e] = (f == 0.0f || f == 1.0f || f == 2.0f) ? (uint8_t)f : 3;
-            }
-        } else {
-          const uint8_t* row = (const uint8_t*)G + snp * ldg + i0;
-          if (i0 + 16 <= n) {
-            __builtin_memcpy(by, __builtin_assume_aligned(row, ALIGN), 16);
-          } else if (ALIGN >= 4) {
-            // the row's end: whole 4-byte words, then the bytes of a split one
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              uint32_t word = 0;
-              if (i0 + 4 * q + 4 <= n) {
-                word = *(const uint32_t*)__builtin_assume_aligned(row + 4 * q, 4);
-              } else {
-                for (int e = 0; e < 3; ++e)
-                  if (i0 + 4 * q + e < n) word |= (uint32_t)row[4 * q + e] << (8 * e);
-              }
-              __builtin_memcpy(by + 4 * q, &word, 4);
-            }
-          } else {
-#pragma unroll
-            for (int e = 0; e < 16; ++e) by[e] = (i0 + e < n) ? row[e] : 0;
-          }
-        }
-      }
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-        if (by[e] > 2) {
-          bad = 1;
-          by[e] = 0;
-        }
-      uint32_t wd[4];
-      __builtin_memcpy(wd, by, 16);
-      if (snp < m_pad) __builtin_memcpy(__builtin_assume_aligned(Gp + kt32(snp, i0, mbp), 16), wd, 16);
-      // the individuals in order: gg sequentially, each projection as even /
-      // odd running sums (t0, t1), one genotype at a time
-      double g2 = red[part][lane][PL], t0[PL], t1[PL];
-#pragma unroll
-      for (int a = 0; a < PL; ++a) t0[a] = t1[a] = 0.0;
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const double d = (double)((wd[e >> 2] >> (8 * (e & 3))) & 255u);
-        g2 += d * d;
-#pragma unroll
-        for (int a = 0; a < PL; ++a) {
-          if (e & 1)
-            t1[a] += qs[a][16 * part + e] * d;
-          else
-            t0[a] += qs[a][16 * part + e] * d;
-        }
-        __builtin_amdgcn_sched_barrier(0);  // one genotype at a time: few LDS values live
-      }
-      red[part][lane][PL] = g2;
-#pragma unroll
-      for (int a = 0; a < PL; ++a) red[part][lane][a] += t0[a] + t1[a];
-    }
-  }
-  for (int part = wid; part < ING_WAVES; part += NW) red[part][lane][PL + 1] = (double)bad;
-  __syncthreads();
-  if (wid != 0 || snp >= m_pad) return;
-#pragma unroll
-  for (int q = 0; q < NV; ++q) {
-    double t = 0.0;
-    for (int w = 0; w < ING_WAVES; ++w) t += red[w][lane][q];
-    ipart[(s0 * NV + q) * mbp + snp] = t;
-  }
-}
-
-template <int PL, int ALIGN, int KIND>
-__global__ void __launch_bounds__(256) k_ingest_slim(IngArgs a) {
-  ingest_tile_slim<PL, ALIGN, KIND>(a, blockIdx.x, blockIdx.y);
-}
-
 // The ingests of several plans' blocks in one launch (per plan m_pad / 64 x S
 // work-groups, flattened).
 template <int PL, int ALIGN, int KIND>
@@ -338,42 +212,35 @@ __global__ void __launch_bounds__(256) k_ingest_fin_batch(BatchArgs<FinArgs> B) 
   ingest_fin_tile<PL>(B.a[k], b - B.start[k]);
 }
 
-template <int PL, int ALIGN, int KIND>
-static void ingest_launch(bool slim, dim3 grid, const IngArgs& ia, hipStream_t st) {
-  if (slim)
-    k_ingest_slim<PL, ALIGN, KIND><<<grid, dim3(256), 0, st>>>(ia);
-  else
-    k_ingest<PL, ALIGN, KIND><<<grid, dim3(64 * ING_WAVES), 0, st>>>(ia);
-}
-
 template <int PL>
 static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const void* d_G, int g_dtype, int64_t ldg) {
   const int S = ingest_splits(p);
   dim3 grid((unsigned)(m_pad / 64), (unsigned)S);
   const Workspace& W = p.ws;
+  const dim3 block(64 * ING_WAVES);
   const IngArgs ia{p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, W.ipart, S};
-  // beside the Z-resident rotation the slim variant, which fits on its CUs
-  const bool slim = rot_zs_active(p) && PL <= 4;
   if (g_dtype == CLAK_G_F16) {
-    ingest_launch<PL, 1, 1>(slim, grid, ia, p.stream);
+    k_ingest<PL, 1, 1><<<grid, block, 0, p.stream>>>(ia);
   } else if (g_dtype == CLAK_G_P2) {
     const bool words = ((uintptr_t)d_G % 4 == 0) && (ldg % 4 == 0);
     if (words)
-      ingest_launch<PL, 4, 2>(slim, grid, ia, p.stream);
+      k_ingest<PL, 4, 2><<<grid, block, 0, p.stream>>>(ia);
     else
-      ingest_launch<PL, 1, 2>(slim, grid, ia, p.stream);
+      k_ingest<PL, 1, 2><<<grid, block, 0, p.stream>>>(ia);
   } else {
     // widest alignment shared by the base address and the row pitch, capped at 16
     const uint64_t bits = (uint64_t)(uintptr_t)d_G | (uint64_t)ldg | 16u;
     const int align = (int)(bits & (~bits + 1));
+#define CLAK_ING(A) k_ingest<PL, A, 0><<<grid, block, 0, p.stream>>>(ia)
     if (align >= 16)
-      ingest_launch<PL, 16, 0>(slim, grid, ia, p.stream);
+      CLAK_ING(16);
     else if (align >= 8)
-      ingest_launch<PL, 8, 0>(slim, grid, ia, p.stream);
+      CLAK_ING(8);
     else if (align >= 4)
-      ingest_launch<PL, 4, 0>(slim, grid, ia, p.stream);
+      CLAK_ING(4);
     else
-      ingest_launch<PL, 1, 0>(slim, grid, ia, p.stream);
+      CLAK_ING(1);
+#undef CLAK_ING
   }
   k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(
       FinArgs{m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv, W.sstat});
