@@ -301,7 +301,10 @@ def stage_flops(stage, w, block):
 
 
 def roofline(prof, w, block, precision, workload, tuning, ms_step):
-    """Roofline of the stage that keeps the GPU busiest per step.
+    """Roofline of the stage that does the most work per step (launches per
+    step x its isolated launch duration: where two streams overlap kernels,
+    each is stretched by the other, so their in-pipeline busy times do not
+    tell which does more work).
 
     achieved = algorithmic flops of one launch x launches per step / the
     stage's busy time per step.  The busy time is the stage's share of a
@@ -310,7 +313,8 @@ def roofline(prof, w, block, precision, workload, tuning, ms_step):
     times the unprofiled step, so it never exceeds the step.  Beside it: the
     mean launch duration in the pipeline (what a rocprofv3 kernel trace of the
     same passes averages) and the isolated one."""
-    dom = max((k for k in prof if prof[k]["launches_per_step"] > 0), key=lambda k: prof[k]["busy_share"])
+    dom = max((k for k in prof if prof[k]["launches_per_step"] > 0),
+              key=lambda k: prof[k]["launches_per_step"] * prof[k]["isolated_launch_ms"])
     d = prof[dom]
     flops = stage_flops(dom, w, block)
     if flops is None:
@@ -652,7 +656,7 @@ def run_cohorts(args, clak, torch):
         "config": {"workload": wname, "cohorts": [{"n": w.n, "t": w.t, "m": w.m} for w in ws], "block": C3_BLOCK,
                    "precision": args.precision, "parallelism": "single GPU"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "k_rot_i8 + k_grid32 (all cohorts)",
+                     "frac": achieved / peak, "traffic": None, "kernel": "k_rot_i8 + k_grid_ring (all cohorts)",
                      "basis": "rotation and grid flops of all cohorts per step / wall time of the step",
                      "peak_source": peak_name},
         "stage_launch_ms_summed_over_cohorts": {k: sum(p[k][0] for p in profs) / args.steps for k in profs[0]},
