@@ -13,15 +13,21 @@
 // A work-group takes 128 SNPs x 32 traits with four waves, one per SIMD; wave
 // w owns the 32 x 32 cells of SNP rows 32 w .. 32 w + 31 and keeps every sum
 // of them in its accumulators: p_L + 2 MFMA tiles of 32 x 32, 64 registers
-// each (320 for p_L = 3, within the 512 registers of one wave per SIMD).
-// (p_L <= 3; larger p_L take the two-stage kernel of k_mixed.hip.)
+// each.  For p_L <= 2 they fit the 256 accumulation registers and one pass
+// over K forms them all.  For p_L = 3 (320 registers) the quadratic sum a
+// takes a first pass over the x o x and d planes and is parked in LDS, and the
+// p_L + 1 linear sums (256 registers) a second pass over the x and operand
+// planes: held in one pass, the compiler kept part of the sums in the
+// architectural registers and moved them through the accumulation registers
+// around the MFMAs (some 200 register moves per 50 MFMAs).  (p_L <= 3; larger
+// p_L take the two-stage kernel of k_mixed.hip.)
 //
 // Staging: a ring of three 32-deep K slices in LDS, filled by direct
 // global-to-LDS loads (global_load_lds_dwordx4) of whole 1 KB MFMA fragments
 // (32 rows x 32 bytes of K, the kt32 layout of every digit plane), two slices
 // in flight while one is multiplied; no staging registers, no LDS stores by
 // the waves.  Wave w loads the x (and x o x) fragments of its own SNP rows and
-// plane w of every trait operand tile.
+// plane w of every trait operand tile of the pass.
 //
 // Work-groups go round-robin over the 8 XCDs.  XCD x owns a contiguous range
 // of the block's SNP tiles and walks all trait groups for sg of them at a
@@ -70,6 +76,52 @@ struct GridArgs {
   CellOut out;
 };
 
+// A pass over K through a three-slot ring in LDS: step s takes the SPS
+// consecutive 32-deep slices SPS s .. SPS s + SPS - 1, in slot s % 3; the LPW
+// fragments of wave w for sub-slice h sit at LDS fragment (h LPW + q) 4 + w
+// (source src(q, slice): a wave-uniform base plus the lane's offset loff into
+// the fragment).  As the rotation's ring: wait for this wave's loads of step s
+// (the next step's stay in flight), barrier (every wave's loads of s have
+// landed, every wave is done with step s - 1), load step s + 2 into the slot of
+// s - 1, multiply step s (body, once per sub-slice, given the lane's address
+// in it).  Past the last slice the loads repeat slice KT - 1 into a slot that
+// is not read again (in bounds).  Ends with no load in flight and a barrier.
+// KT must be a multiple of SPS.
+template <int LPW, int SPS, class Src, class Body>
+__device__ __forceinline__ void grid_kloop(int KT, int w, int lane, uint32_t loff, int8_t* s0, int8_t* s1, int8_t* s2,
+                                           Src src, Body body) {
+  int8_t* const slots[3] = {s0, s1, s2};
+  const int NS = KT / SPS;
+  auto issue = [&](int u, int s) {
+    int8_t* dst = slots[u];
+#pragma unroll
+    for (int h = 0; h < SPS; ++h)
+#pragma unroll
+      for (int q = 0; q < LPW; ++q)
+        __builtin_amdgcn_global_load_lds(src(q, min(SPS * s + h, KT - 1)) + loff,
+                                         (lds_ptr_t)(dst + ((h * LPW + q) * 4 + w) * 1024), 16, 0, 0);
+  };
+  auto step = [&](int u, int s) {
+    wait_vm<LPW * SPS>();
+    lds_barrier();
+    issue((u + 2) % 3, s + 2);
+#pragma unroll
+    for (int h = 0; h < SPS; ++h) body((const int8_t*)(slots[u] + h * LPW * 4 * 1024 + 16 * lane));
+  };
+  issue(0, 0);
+  issue(1, 1);
+  int s = 0;
+  for (; s + 3 <= NS; s += 3) {
+    step(0, s);
+    step(1, s + 1);
+    step(2, s + 2);
+  }
+  if (s < NS) step(0, s);
+  if (s + 1 < NS) step(1, s + 1);
+  wait_vm<0>();     // no load is left in flight
+  __syncthreads();  // the ring is free for the next pass or the epilogue
+}
+
 // Work-group bid of the grid of one plan's block.
 template <int PL, bool FULL>
 __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
@@ -105,88 +157,112 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
   const uint32_t loff = 32 * (lane & 31) + 16 * (lane >> 5);
   const int64_t vgrp = (j0 >> 5) * 32 * NV;  // first operand row of the trait group
 
-  v16i acc[NT][4];
+  // One pass over K holds every sum of a cell (p_L + 2 tiles x four weight
+  // groups) in the accumulators when they fit the 256 accumulation registers
+  // (p_L <= 2).  For p_L = 3 (320 registers) the compiler would keep part of
+  // them in the architectural registers and shuttle them through the
+  // accumulation registers around every MFMA, so the quadratic sum a goes
+  // first, in a pass of its own over the x o x and d planes, and is parked in
+  // LDS (16 doubles per lane); the linear sums follow in a second pass.
+  constexpr bool TWO = NT * 64 > 256;
+  constexpr int NTB = TWO ? NV : NT;  // tiles of the main pass
+  v16i acc[NTB][4];
 #pragma unroll
-  for (int q = 0; q < NT; ++q)
+  for (int q = 0; q < NTB; ++q)
 #pragma unroll
     for (int g = 0; g < 4; ++g) acc[q][g] = (v16i){};
+  // the quadratic sums parked between the passes: [r][lane] doubles per wave,
+  // waves 0, 1 past byte ASAVE_OFF of slot 0, waves 2, 3 of slot 1 (free of
+  // the second pass's 32 KB slices and of the epilogue's 33.8 KB stages)
+  constexpr int ASAVE_OFF = 36 * 1024;
+  static_assert(!TWO || (ASAVE_OFF + 2 * 16 * 64 * 8 <= GR_SLOT && ASAVE_OFF >= 8 * GR_STAGE * 4 &&
+                         ASAVE_OFF >= (4 + NV) * 4 * 1024),
+                "parked sums must not overlap the ring or the stages");
+  double* asave = (double*)((w < 2 ? smem0 : smem1) + ASAVE_OFF) + (w & 1) * 16 * 64 + lane;
 
-  auto slot = [&](auto u) -> int8_t* {
-    if constexpr (decltype(u)::value == 0) return smem0;
-    else if constexpr (decltype(u)::value == 1) return smem1;
-    else return smem2;
+  // The ten digit products of total weight g = a + b <= 3 of one slice into
+  // the four weight-group accumulators A[g].
+  auto products = [](const v4i* a, const v4i* b, v16i(&A)[4]) {
+    A[0] = mfma32_i8(a[0], b[0], A[0]);
+    A[1] = mfma32_i8(a[0], b[1], A[1]);
+    A[2] = mfma32_i8(a[0], b[2], A[2]);
+    A[3] = mfma32_i8(a[0], b[3], A[3]);
+    A[1] = mfma32_i8(a[1], b[0], A[1]);
+    A[2] = mfma32_i8(a[1], b[1], A[2]);
+    A[3] = mfma32_i8(a[1], b[2], A[3]);
+    A[2] = mfma32_i8(a[2], b[0], A[2]);
+    A[3] = mfma32_i8(a[2], b[1], A[3]);
+    A[3] = mfma32_i8(a[3], b[0], A[3]);
   };
-  using U0 = std::integral_constant<int, 0>;
-  using U1 = std::integral_constant<int, 1>;
-  using U2 = std::integral_constant<int, 2>;
 
-  {
-    // slice s into slot u: fragment q * 4 + w of the slice, for q < LPW.  The
-    // source is a wave-uniform base plus the lane's offset into the fragment.
-    auto issue = [&](auto u, int s) {
-      int8_t* dst = slot(u);
+  // source of digit plane p of the x (xq: x o x) fragments of this wave's SNP tile
+  auto xsrc = [&](int p, int s) { return Xd + p * xplane + ((int64_t)s * mbp + i0 + 32 * w) * 32; };
+  // plane w of trait operand entry e (d for e = PL + 1)
+  auto tsrc = [&](int e, int s) {
+    return e <= PL ? Vd + w * vplane + ((int64_t)s * tp * NV + vgrp + 32 * e) * 32
+                   : Dd + w * dplane + ((int64_t)s * tp + j0) * 32;
+  };
+
+  if constexpr (TWO) {
+    // pass A: a = d^T (x o x), two slices per ring step (ten MFMAs per slice
+    // would not cover the loads' latency); fragments per slice: x o x planes
+    // (0 .. 15), d planes (16 .. 19)
+    v16i accA[4];
 #pragma unroll
-      for (int q = 0; q < LPW; ++q) {
-        const int8_t* src;
-        if (q < FA / 4) {  // digit plane q of x (q < 4) or q - 4 of x o x, SNP row tile w
-          src = Xd + q * xplane + ((int64_t)s * mbp + i0 + 32 * w) * 32;
-        } else {  // entry e of the trait operand (d for e = PL + 1), plane w
-          const int e = q - FA / 4;
-          if (e <= PL)
-            src = Vd + w * vplane + ((int64_t)s * tp * NV + vgrp + 32 * e) * 32;
-          else
-            src = Dd + w * dplane + ((int64_t)s * tp + j0) * 32;
-        }
-        __builtin_amdgcn_global_load_lds(src + loff, (lds_ptr_t)(dst + (q * 4 + w) * 1024), 16, 0, 0);
-      }
-    };
-    // As the rotation's ring: wait for this wave's loads of slice s (the next
-    // slice's stay in flight), barrier (every wave's loads of s have landed,
-    // every wave is done with slice s - 1), load slice s + 2 into the slot of
-    // s - 1, multiply slice s.  Past the last slice the load repeats slice
-    // KT - 1 into a slot that is not read again (in bounds).
-    auto step = [&](auto u, int s) {
-      wait_vm<LPW>();
-      lds_barrier();
-      const int8_t* sp = slot(u) + 16 * lane;
-      v4i xa[4], xq[4];
+    for (int g = 0; g < 4; ++g) accA[g] = (v16i){};
+    grid_kloop<5, 2>(KT, w, lane, loff, smem0, smem1, smem2,
+          [&](int q, int s) { return q < 4 ? xsrc(4 + q, s) : tsrc(PL + 1, s); },
+          [&](const int8_t* sp) {
+            v4i xq[4], b[4];
 #pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
-        xq[p] = *(const v4i*)(sp + (16 + p * 4 + w) * 1024);
-      }
-      issue(std::integral_constant<int, (decltype(u)::value + 2) % 3>{}, min(s + 2, KT - 1));
+            for (int p = 0; p < 4; ++p) {
+              xq[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
+              b[p] = *(const v4i*)(sp + (16 + p) * 1024);
+            }
+            products(xq, b, accA);
+          });
 #pragma unroll
-      for (int tt = 0; tt < NT; ++tt) {
-        v4i b[4];
+    for (int r = 0; r < 16; ++r) asave[r * 64] = g32_value(accA, r);
+    // pass B: the linear sums; fragments: x planes (0 .. 15), operand entries e (16 + 4 e + p)
+    grid_kloop<4 + NV, 1>(KT, w, lane, loff, smem0, smem1, smem2,
+          [&](int q, int s) { return q < 4 ? xsrc(q, s) : tsrc(q - 4, s); },
+          [&](const int8_t* sp) {
+            // the next entry's operand fragments are read while this entry's
+            // MFMAs run (two register sets), so an LDS read latency is exposed
+            // once per slice, not once per entry
+            v4i xa[4], b[2][4];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + (FA + 4 * tt + p) * 1024);
-        const v4i* a = tt == NT - 1 ? xq : xa;
-        v16i(&A)[4] = acc[tt];
-        A[0] = mfma32_i8(a[0], b[0], A[0]);
-        A[1] = mfma32_i8(a[0], b[1], A[1]);
-        A[2] = mfma32_i8(a[0], b[2], A[2]);
-        A[3] = mfma32_i8(a[0], b[3], A[3]);
-        A[1] = mfma32_i8(a[1], b[0], A[1]);
-        A[2] = mfma32_i8(a[1], b[1], A[2]);
-        A[3] = mfma32_i8(a[1], b[2], A[3]);
-        A[2] = mfma32_i8(a[2], b[0], A[2]);
-        A[3] = mfma32_i8(a[2], b[1], A[3]);
-        A[3] = mfma32_i8(a[3], b[0], A[3]);
-      }
-    };
-    issue(U0{}, 0);
-    issue(U1{}, min(1, KT - 1));
-    int s = 0;
-    for (; s + 3 <= KT; s += 3) {
-      step(U0{}, s);
-      step(U1{}, s + 1);
-      step(U2{}, s + 2);
-    }
-    if (s < KT) step(U0{}, s);
-    if (s + 1 < KT) step(U1{}, s + 1);
-    wait_vm<0>();     // no load is left in flight
-    __syncthreads();  // the ring is free: the epilogue reuses it
+            for (int p = 0; p < 4; ++p) {
+              xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
+              b[0][p] = *(const v4i*)(sp + (16 + p) * 1024);
+            }
+#pragma unroll
+            for (int tt = 0; tt < NV; ++tt) {
+              if (tt + 1 < NV)
+#pragma unroll
+                for (int p = 0; p < 4; ++p) b[(tt + 1) & 1][p] = *(const v4i*)(sp + (16 + 4 * (tt + 1) + p) * 1024);
+              products(xa, b[tt & 1], acc[tt]);
+            }
+          });
+  } else {
+    // one pass; fragments: x planes (0 .. 15), x o x planes (16 .. 31), tile tt plane p (32 + 4 tt + p)
+    grid_kloop<LPW, 1>(KT, w, lane, loff, smem0, smem1, smem2,
+          [&](int q, int s) { return q < 8 ? xsrc(q, s) : tsrc(q - 8, s); },
+          [&](const int8_t* sp) {
+            v4i xa[4], xq[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+              xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
+              xq[p] = *(const v4i*)(sp + (16 + p * 4 + w) * 1024);
+            }
+#pragma unroll
+            for (int tt = 0; tt < NT; ++tt) {
+              v4i b[4];
+#pragma unroll
+              for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + (FA + 4 * tt + p) * 1024);
+              products(tt == NT - 1 ? xq : xa, b, acc[tt]);
+            }
+          });
   }
 
   // per-lane trait (column lane % 32 of every tile) and its parameters
@@ -236,7 +312,11 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
     double cv[FULL ? PL : 1];
 #pragma unroll
     for (int e = 0; e < NT; ++e) {
-      const double raw = g32_value(acc[e], r) * sc[e];
+      double raw;
+      if constexpr (TWO)
+        raw = (e == NT - 1 ? asave[r * 64] : g32_value(acc[e < NTB ? e : 0], r)) * sc[e];
+      else
+        raw = g32_value(acc[e < NTB ? e : 0], r) * sc[e];
       if (e < PL) {
         const double v = raw * gx;
         cc += v * v;

@@ -53,8 +53,7 @@ SHAPES = [  # n, p_L, t, m_blk, max_block
 def test_ring_grid_tiles_and_addresses(n, pL, t, m_blk, max_block, sg):
     np_, mbp, tp = rnd(n, KPAD), rnd(max_block, SNP_PAD), rnd(t, TRAIT_PAD)
     NV, NT = pL + 1, pL + 2
-    FA, FS = 32, 32 + 4 * NT
-    LPW = FS // 4
+    two = NT * 64 > 256  # p_L = 3: the quadratic sums in a pass of their own
     st, tg, xcd, ns, ng = work_map(m_blk, t, sg)
     key = st * ng + tg
     assert len(key) == ns * ng and len(np.unique(key)) == len(key)
@@ -69,23 +68,41 @@ def test_ring_grid_tiles_and_addresses(n, pL, t, m_blk, max_block, sg):
     xplane, vplane, dplane = mbp * np_, tp * NV * np_, tp * np_
     vgrp = (j0 // 32) * 32 * NV
     s = slices.max()
-    for w in range(4):
-        for q in range(LPW):
-            if q < FA // 4:
-                end = q * xplane + (s * mbp + i0 + 32 * w) * 32 + 1024
-                assert (end <= 8 * xplane).all(), ("x digits", q, w)
-            else:
-                e = q - FA // 4
-                if e <= pL:
-                    end = w * vplane + (s * tp * NV + vgrp + 32 * e) * 32 + 1024
-                    assert (end <= 4 * vplane).all(), ("operand", e, w)
-                else:
-                    end = w * dplane + (s * tp + j0) * 32 + 1024
-                    assert (end <= 4 * dplane).all(), ("d", w)
-            assert (q * 4 + w) * 1024 + 1024 <= GR_SLOT
+
+    def x_end(p, w):  # digit plane p of x (p < 4) or x o x (p >= 4), SNP tile w
+        return p * xplane + (s * mbp + i0 + 32 * w) * 32 + 1024
+
+    def t_end(e, w):  # plane w of operand entry e (d for e = p_L + 1)
+        if e <= pL:
+            return w * vplane + (s * tp * NV + vgrp + 32 * e) * 32 + 1024, 4 * vplane
+        return w * dplane + (s * tp + j0) * 32 + 1024, 4 * dplane
+
+    # the passes: (loads per wave per slice, slices per ring step, source of
+    # load q, LDS bound) as the kernel issues them; the second pass of the
+    # two-pass kernel stays below the sums parked after the first
+    ASAVE_OFF = 36 * 1024
+    if two:
+        passes = [(5, 2, lambda q, w: ("x", 4 + q) if q < 4 else ("t", pL + 1), GR_SLOT),
+                  (4 + NV, 1, lambda q, w: ("x", q) if q < 4 else ("t", q - 4), ASAVE_OFF)]
+    else:
+        passes = [(8 + NT, 1, lambda q, w: ("x", q) if q < 8 else ("t", q - 8), GR_SLOT)]
+    for lpw, sps, src, bound in passes:
+        assert KT % sps == 0
+        for w in range(4):
+            for h in range(sps):
+                for q in range(lpw):
+                    kind, e = src(q, w)
+                    if kind == "x":
+                        assert (x_end(e, w) <= 8 * xplane).all(), ("x digits", e, w)
+                    else:
+                        end, size = t_end(e, w)
+                        assert (end <= size).all(), ("operand", e, w)
+                    assert ((h * lpw + q) * 4 + w) * 1024 + 1024 <= bound
     # epilogue LDS: four waves' [32][33] double stages, then the SNP tables
     assert 4 * GR_STAGE * 8 + 128 * (2 + pL) * 8 <= GR_SLOT
     assert 4 * GR_STAGE <= GR_SLOT
+    if two:  # parked sums of two waves per slot after the stages, inside the slot
+        assert 4 * GR_STAGE * 8 <= ASAVE_OFF and ASAVE_OFF + 2 * 16 * 64 * 8 <= GR_SLOT
 
 
 def test_trait_operand_rows_of_a_group():
