@@ -22,12 +22,14 @@
 // around the MFMAs (some 200 register moves per 50 MFMAs).  (p_L <= 3; larger
 // p_L take the two-stage kernel of k_mixed.hip.)
 //
-// Staging: a ring of three 32-deep K slices in LDS, filled by direct
-// global-to-LDS loads (global_load_lds_dwordx4) of whole 1 KB MFMA fragments
-// (32 rows x 32 bytes of K, the kt32 layout of every digit plane), two slices
-// in flight while one is multiplied; no staging registers, no LDS stores by
-// the waves.  Wave w loads the x (and x o x) fragments of its own SNP rows and
-// plane w of every trait operand tile of the pass.
+// Staging: a ring of three 32-deep K slices, two in flight while one is
+// multiplied.  The trait operand fragments, which all four waves read, go to
+// LDS by direct global-to-LDS loads (global_load_lds_dwordx4) of whole 1 KB
+// MFMA fragments (32 rows x 32 bytes of K, the kt32 layout of every digit
+// plane), wave w loading plane w of every operand tile of the pass; no LDS
+// stores by the waves.  The x (and x o x) fragments of a wave's own SNP rows,
+// which no other wave reads, go straight into its registers (three sets), so
+// the LDS carries only the shared operand.
 //
 // Work-groups go round-robin over the 8 XCDs.  XCD x owns a contiguous range
 // of the block's SNP tiles and walks all trait groups for sg of them at a
@@ -49,16 +51,13 @@ namespace clak {
 template <int PL>
 struct GridTiles {
   static constexpr int NT = PL + 2;
-  // fragments per slice: x planes of the 4 SNP row tiles, x o x planes, then
-  // 4 planes of each trait operand tile
-  static constexpr int FA = 32;
+  // LDS fragments per slice at most: 4 planes of each trait operand tile (the
+  // SNP tiles' x and x o x planes go to registers)
   static constexpr int FB = 4 * NT;
-  static constexpr int FS = FA + FB;
-  static constexpr int LPW = FS / 4;  // direct loads per wave per slice
   static_assert(PL >= 1 && PL <= 3, "one pass holds p_L <= 3");
 };
 
-constexpr int GR_SLOT = 52 * 1024;  // largest slice: 16 + 16 + 4 x 5 fragments
+constexpr int GR_SLOT = 52 * 1024;  // a ring slot; after the K loop the epilogue's stages and the parked sums
 constexpr int GR_STAGE = 32 * 33;   // per-wave epilogue staging: 32 traits x (32 SNPs + 1)
 
 // Arguments of the grid contraction of one plan's block (see grid_tile).
@@ -76,21 +75,25 @@ struct GridArgs {
   CellOut out;
 };
 
-// A pass over K through a three-slot ring in LDS: step s takes the SPS
-// consecutive 32-deep slices SPS s .. SPS s + SPS - 1, in slot s % 3; the LPW
-// fragments of wave w for sub-slice h sit at LDS fragment (h LPW + q) 4 + w
-// (source src(q, slice): a wave-uniform base plus the lane's offset loff into
-// the fragment).  As the rotation's ring: wait for this wave's loads of step s
-// (the next step's stay in flight), barrier (every wave's loads of s have
-// landed, every wave is done with step s - 1), load step s + 2 into the slot of
-// s - 1, multiply step s (body, once per sub-slice, given the lane's address
-// in it).  Past the last slice the loads repeat slice KT - 1 into a slot that
-// is not read again (in bounds).  Ends with no load in flight and a barrier.
-// KT must be a multiple of SPS.
-template <int LPW, int SPS, class Src, class Body>
+// A pass over K through a three-slot ring: step s takes the SPS consecutive
+// 32-deep slices SPS s .. SPS s + SPS - 1.  The trait operand fragments, which
+// the four waves share, go through LDS slot s % 3: the LPW fragments of wave w
+// for sub-slice h sit at LDS fragment (h LPW + q) 4 + w (source src(q, slice):
+// a wave-uniform base plus the lane's offset loff into the fragment).  The
+// XPW fragments of the wave's own SNP tile go straight into registers, one
+// set per slot (source xs(q, slice)), so they cost no LDS bandwidth.  As the
+// rotation's ring: wait for this wave's loads of step s (the next step's stay
+// in flight), barrier (every wave's loads of s have landed, every wave is done
+// with step s - 1), load step s + 2 into the slot and register set of s - 1,
+// multiply step s (body, once per sub-slice, given the lane's address in the
+// slot and the sub-slice's registers).  Past the last slice the loads repeat
+// slice KT - 1 into a slot that is not read again (in bounds).  Ends with no
+// load in flight and a barrier.  KT must be a multiple of SPS.
+template <int LPW, int XPW, int SPS, class Src, class XSrc, class Body>
 __device__ __forceinline__ void grid_kloop(int KT, int w, int lane, uint32_t loff, int8_t* s0, int8_t* s1, int8_t* s2,
-                                           Src src, Body body) {
+                                           Src src, XSrc xs, Body body) {
   int8_t* const slots[3] = {s0, s1, s2};
+  v4i xr[3][SPS * XPW];
   const int NS = KT / SPS;
   auto issue = [&](int u, int s) {
     int8_t* dst = slots[u];
@@ -100,13 +103,18 @@ __device__ __forceinline__ void grid_kloop(int KT, int w, int lane, uint32_t lof
       for (int q = 0; q < LPW; ++q)
         __builtin_amdgcn_global_load_lds(src(q, min(SPS * s + h, KT - 1)) + loff,
                                          (lds_ptr_t)(dst + ((h * LPW + q) * 4 + w) * 1024), 16, 0, 0);
+#pragma unroll
+    for (int h = 0; h < SPS; ++h)
+#pragma unroll
+      for (int q = 0; q < XPW; ++q) xr[u][h * XPW + q] = *(const v4i*)(xs(q, min(SPS * s + h, KT - 1)) + loff);
   };
   auto step = [&](int u, int s) {
-    wait_vm<LPW * SPS>();
+    wait_vm<(LPW + XPW) * SPS>();
     lds_barrier();
     issue((u + 2) % 3, s + 2);
 #pragma unroll
-    for (int h = 0; h < SPS; ++h) body((const int8_t*)(slots[u] + h * LPW * 4 * 1024 + 16 * lane));
+    for (int h = 0; h < SPS; ++h)
+      body((const int8_t*)(slots[u] + h * LPW * 4 * 1024 + 16 * lane), (const v4i*)&xr[u][h * XPW]);
   };
   issue(0, 0);
   issue(1, 1);
@@ -137,8 +145,8 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
   const uint32_t flags = ga.flags;
   const CellOut& out = ga.out;
   using GT = GridTiles<PL>;
-  constexpr int NV = PL + 1, NT = GT::NT, FA = GT::FA, LPW = GT::LPW;
-  static_assert(GR_SLOT >= GT::FS * 1024, "slot size");
+  constexpr int NV = PL + 1, NT = GT::NT;
+  static_assert(GR_SLOT >= GT::FB * 1024, "slot size");
   __shared__ __attribute__((aligned(1024))) int8_t smem0[GR_SLOT];
   __shared__ __attribute__((aligned(1024))) int8_t smem1[GR_SLOT];
   __shared__ __attribute__((aligned(1024))) int8_t smem2[GR_SLOT];
@@ -176,7 +184,7 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
   // the second pass's 32 KB slices and of the epilogue's 33.8 KB stages)
   constexpr int ASAVE_OFF = 36 * 1024;
   static_assert(!TWO || (ASAVE_OFF + 2 * 16 * 64 * 8 <= GR_SLOT && ASAVE_OFF >= 8 * GR_STAGE * 4 &&
-                         ASAVE_OFF >= (4 + NV) * 4 * 1024),
+                         ASAVE_OFF >= NV * 4 * 1024),
                 "parked sums must not overlap the ring or the stages");
   double* asave = (double*)((w < 2 ? smem0 : smem1) + ASAVE_OFF) + (w & 1) * 16 * 64 + lane;
 
@@ -205,62 +213,50 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
 
   if constexpr (TWO) {
     // pass A: a = d^T (x o x), two slices per ring step (ten MFMAs per slice
-    // would not cover the loads' latency); fragments per slice: x o x planes
-    // (0 .. 15), d planes (16 .. 19)
+    // would not cover the loads' latency); LDS fragments per slice: the d
+    // planes; registers: the wave's x o x planes
     v16i accA[4];
 #pragma unroll
     for (int g = 0; g < 4; ++g) accA[g] = (v16i){};
-    grid_kloop<5, 2>(KT, w, lane, loff, smem0, smem1, smem2,
-          [&](int q, int s) { return q < 4 ? xsrc(4 + q, s) : tsrc(PL + 1, s); },
-          [&](const int8_t* sp) {
-            v4i xq[4], b[4];
+    grid_kloop<1, 4, 2>(KT, w, lane, loff, smem0, smem1, smem2, [&](int, int s) { return tsrc(PL + 1, s); },
+          [&](int q, int s) { return xsrc(4 + q, s); },
+          [&](const int8_t* sp, const v4i* xq) {
+            v4i b[4];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-              xq[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
-              b[p] = *(const v4i*)(sp + (16 + p) * 1024);
-            }
+            for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + p * 1024);
             products(xq, b, accA);
           });
 #pragma unroll
     for (int r = 0; r < 16; ++r) asave[r * 64] = g32_value(accA, r);
-    // pass B: the linear sums; fragments: x planes (0 .. 15), operand entries e (16 + 4 e + p)
-    grid_kloop<4 + NV, 1>(KT, w, lane, loff, smem0, smem1, smem2,
-          [&](int q, int s) { return q < 4 ? xsrc(q, s) : tsrc(q - 4, s); },
-          [&](const int8_t* sp) {
+    // pass B: the linear sums; LDS fragments: operand entry e plane p at 4 e + p; registers: the x planes
+    grid_kloop<NV, 4, 1>(KT, w, lane, loff, smem0, smem1, smem2, [&](int q, int s) { return tsrc(q, s); },
+          [&](int q, int s) { return xsrc(q, s); },
+          [&](const int8_t* sp, const v4i* xa) {
             // the next entry's operand fragments are read while this entry's
             // MFMAs run (two register sets), so an LDS read latency is exposed
             // once per slice, not once per entry
-            v4i xa[4], b[2][4];
+            v4i b[2][4];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-              xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
-              b[0][p] = *(const v4i*)(sp + (16 + p) * 1024);
-            }
+            for (int p = 0; p < 4; ++p) b[0][p] = *(const v4i*)(sp + p * 1024);
 #pragma unroll
             for (int tt = 0; tt < NV; ++tt) {
               if (tt + 1 < NV)
 #pragma unroll
-                for (int p = 0; p < 4; ++p) b[(tt + 1) & 1][p] = *(const v4i*)(sp + (16 + 4 * (tt + 1) + p) * 1024);
+                for (int p = 0; p < 4; ++p) b[(tt + 1) & 1][p] = *(const v4i*)(sp + (4 * (tt + 1) + p) * 1024);
               products(xa, b[tt & 1], acc[tt]);
             }
           });
   } else {
-    // one pass; fragments: x planes (0 .. 15), x o x planes (16 .. 31), tile tt plane p (32 + 4 tt + p)
-    grid_kloop<LPW, 1>(KT, w, lane, loff, smem0, smem1, smem2,
-          [&](int q, int s) { return q < 8 ? xsrc(q, s) : tsrc(q - 8, s); },
-          [&](const int8_t* sp) {
-            v4i xa[4], xq[4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-              xa[p] = *(const v4i*)(sp + (p * 4 + w) * 1024);
-              xq[p] = *(const v4i*)(sp + (16 + p * 4 + w) * 1024);
-            }
+    // one pass; LDS fragments: tile tt plane p at 4 tt + p; registers: the x, then the x o x planes
+    grid_kloop<NT, 8, 1>(KT, w, lane, loff, smem0, smem1, smem2, [&](int q, int s) { return tsrc(q, s); },
+          [&](int q, int s) { return xsrc(q, s); },
+          [&](const int8_t* sp, const v4i* xr) {
 #pragma unroll
             for (int tt = 0; tt < NT; ++tt) {
               v4i b[4];
 #pragma unroll
-              for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + (FA + 4 * tt + p) * 1024);
-              products(tt == NT - 1 ? xq : xa, b, acc[tt]);
+              for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + (4 * tt + p) * 1024);
+              products(tt == NT - 1 ? xr + 4 : xr, b, acc[tt]);
             }
           });
   }

@@ -5,9 +5,9 @@ XCD grouping sg:
 * the work-group -> (SNP tile, trait group) map covers every (128-SNP tile,
   32-trait group) pair of the block exactly once, and the SNP tiles of one
   XCD are a contiguous range;
-* every direct-load fragment (x and x o x digit planes, the trait operand
-  planes, the d planes), for every K slice the ring loads including the
-  clamped loads past the last slice, lies inside its buffer, and its LDS
+* every fragment the ring loads (the trait operand and d planes into LDS,
+  the x and x o x digit planes into registers), for every K slice including
+  the clamped loads past the last slice, lies inside its buffer, and every LDS
   destination inside its ring slot;
 * the per-wave epilogue stages and the SNP tables fit their LDS slots.
 
@@ -77,27 +77,26 @@ def test_ring_grid_tiles_and_addresses(n, pL, t, m_blk, max_block, sg):
             return w * vplane + (s * tp * NV + vgrp + 32 * e) * 32 + 1024, 4 * vplane
         return w * dplane + (s * tp + j0) * 32 + 1024, 4 * dplane
 
-    # the passes: (loads per wave per slice, slices per ring step, source of
-    # load q, LDS bound) as the kernel issues them; the second pass of the
-    # two-pass kernel stays below the sums parked after the first
+    # the passes as the kernel issues them: (LDS loads per wave per slice,
+    # register loads per wave per slice, slices per ring step, operand entry
+    # of LDS load q, digit plane of register load q, LDS bound); the second
+    # pass of the two-pass kernel stays below the sums parked after the first
     ASAVE_OFF = 36 * 1024
     if two:
-        passes = [(5, 2, lambda q, w: ("x", 4 + q) if q < 4 else ("t", pL + 1), GR_SLOT),
-                  (4 + NV, 1, lambda q, w: ("x", q) if q < 4 else ("t", q - 4), ASAVE_OFF)]
+        passes = [(1, 4, 2, lambda q: pL + 1, lambda q: 4 + q, GR_SLOT),
+                  (NV, 4, 1, lambda q: q, lambda q: q, ASAVE_OFF)]
     else:
-        passes = [(8 + NT, 1, lambda q, w: ("x", q) if q < 8 else ("t", q - 8), GR_SLOT)]
-    for lpw, sps, src, bound in passes:
+        passes = [(NT, 8, 1, lambda q: q, lambda q: q, GR_SLOT)]
+    for lpw, xpw, sps, ent, plane, bound in passes:
         assert KT % sps == 0
         for w in range(4):
             for h in range(sps):
                 for q in range(lpw):
-                    kind, e = src(q, w)
-                    if kind == "x":
-                        assert (x_end(e, w) <= 8 * xplane).all(), ("x digits", e, w)
-                    else:
-                        end, size = t_end(e, w)
-                        assert (end <= size).all(), ("operand", e, w)
+                    end, size = t_end(ent(q), w)
+                    assert (end <= size).all(), ("operand", ent(q), w)
                     assert ((h * lpw + q) * 4 + w) * 1024 + 1024 <= bound
+                for q in range(xpw):
+                    assert (x_end(plane(q), w) <= 8 * xplane).all(), ("x digits", plane(q), w)
     # epilogue LDS: four waves' [32][33] double stages, then the SNP tables
     assert 4 * GR_STAGE * 8 + 128 * (2 + pL) * 8 <= GR_SLOT
     assert 4 * GR_STAGE <= GR_SLOT
