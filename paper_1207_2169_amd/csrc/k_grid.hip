@@ -85,8 +85,8 @@ struct GridArgs {
 // rotation's ring: wait for this wave's loads of step s (the next step's stay
 // in flight), barrier (every wave's loads of s have landed, every wave is done
 // with step s - 1), load step s + 2 into the slot and register set of s - 1,
-// multiply step s (body, once per sub-slice, given the lane's address in the
-// slot and the sub-slice's registers).  Past the last slice the loads repeat
+// multiply step s (body, once per sub-slice h, given the lane's address in
+// the slot, the sub-slice's registers and h).  Past the last slice the loads repeat
 // slice KT - 1 into a slot that is not read again (in bounds).  Ends with no
 // load in flight and a barrier.  KT must be a multiple of SPS.
 template <int LPW, int XPW, int SPS, class Src, class XSrc, class Body>
@@ -114,7 +114,7 @@ __device__ __forceinline__ void grid_kloop(int KT, int w, int lane, uint32_t lof
     issue((u + 2) % 3, s + 2);
 #pragma unroll
     for (int h = 0; h < SPS; ++h)
-      body((const int8_t*)(slots[u] + h * LPW * 4 * 1024 + 16 * lane), (const v4i*)&xr[u][h * XPW]);
+      body((const int8_t*)(slots[u] + h * LPW * 4 * 1024 + 16 * lane), (const v4i*)&xr[u][h * XPW], h);
   };
   issue(0, 0);
   issue(1, 1);
@@ -213,25 +213,31 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
 
   if constexpr (TWO) {
     // pass A: a = d^T (x o x), two slices per ring step (ten MFMAs per slice
-    // would not cover the loads' latency); LDS fragments per slice: the d
-    // planes; registers: the wave's x o x planes
-    v16i accA[4];
+    // would not cover the loads' latency), each slice of a step into its own
+    // set of the four accumulators (two independent MFMA chains per weight
+    // group; the sets are added exactly in int32 at the end); LDS fragments
+    // per slice: the d planes; registers: the wave's x o x planes
+    v16i accA[2][4];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) accA[g] = (v16i){};
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) accA[h][g] = (v16i){};
     grid_kloop<1, 4, 2>(KT, w, lane, loff, smem0, smem1, smem2, [&](int, int s) { return tsrc(PL + 1, s); },
           [&](int q, int s) { return xsrc(4 + q, s); },
-          [&](const int8_t* sp, const v4i* xq) {
+          [&](const int8_t* sp, const v4i* xq, int h) {
             v4i b[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) b[p] = *(const v4i*)(sp + p * 1024);
-            products(xq, b, accA);
+            products(xq, b, accA[h]);
           });
 #pragma unroll
-    for (int r = 0; r < 16; ++r) asave[r * 64] = g32_value(accA, r);
+    for (int g = 0; g < 4; ++g) accA[0][g] += accA[1][g];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) asave[r * 64] = g32_value(accA[0], r);
     // pass B: the linear sums; LDS fragments: operand entry e plane p at 4 e + p; registers: the x planes
     grid_kloop<NV, 4, 1>(KT, w, lane, loff, smem0, smem1, smem2, [&](int q, int s) { return tsrc(q, s); },
           [&](int q, int s) { return xsrc(q, s); },
-          [&](const int8_t* sp, const v4i* xa) {
+          [&](const int8_t* sp, const v4i* xa, int) {
             // the next entry's operand fragments are read while this entry's
             // MFMAs run (two register sets), so an LDS read latency is exposed
             // once per slice, not once per entry
@@ -250,7 +256,7 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
     // one pass; LDS fragments: tile tt plane p at 4 tt + p; registers: the x, then the x o x planes
     grid_kloop<NT, 8, 1>(KT, w, lane, loff, smem0, smem1, smem2, [&](int q, int s) { return tsrc(q, s); },
           [&](int q, int s) { return xsrc(q, s); },
-          [&](const int8_t* sp, const v4i* xr) {
+          [&](const int8_t* sp, const v4i* xr, int) {
 #pragma unroll
             for (int tt = 0; tt < NT; ++tt) {
               v4i b[4];
@@ -361,16 +367,19 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
       const int so = tr * 33 + sn;
       const double bv = sb[so], sv = sse[so];
       const uint8_t fv = sfl[so];
-      // the p-value as store_snp forms it, from the staged b and SE
-      const double pv = fv ? __builtin_nan("") : erfc(fabs(bv / sv) * M_SQRT1_2);
       if (out.f64) {
         ((double*)out.b)[o * bstride + boff] = bv;
         ((double*)out.se)[o] = sv;
-        if (want_p) ((double*)out.pval)[o] = pv;
       } else {
         ((float*)out.b)[o * bstride + boff] = (float)bv;
         ((float*)out.se)[o] = (float)sv;
-        if (want_p) ((float*)out.pval)[o] = (float)pv;
+      }
+      if (want_p) {  // the p-value as store_snp forms it, from the staged b and SE
+        const double pv = fv ? __builtin_nan("") : erfc(fabs(bv / sv) * M_SQRT1_2);
+        if (out.f64)
+          ((double*)out.pval)[o] = pv;
+        else
+          ((float*)out.pval)[o] = (float)pv;
       }
       if (out.flags) out.flags[o] = fv;
     }

@@ -6,7 +6,8 @@
 //   r' = x^T D e             (= W_R^T Y_j - c^T S_TL^{-1} b_T)
 //   a  = x^T D x             (= W_R^T W_R)
 //   s  = a - ||c'||^2        (Schur complement, = 1 / [S^{-1}]_pp)
-//   b_snp = r' / s,  Var(b_snp) = 1 / s  (times s2_j under CLAK_VAR_PAPER)
+//   b_snp = r' / s,  Var(b_snp) = 1 / s  (times s2_j under CLAK_VAR_PAPER);
+//   one reciprocal 1 / s serves both (b_snp = r' (1 / s))
 //   b_cov = u - L^{-T} c' b_snp - gamma b_snp   (gamma undoes the centring)
 //   z = b_snp / SE, p = erfc(|z| / sqrt 2)     (optional)
 #pragma once
@@ -50,9 +51,9 @@ __device__ __forceinline__ void schur_store(const double* c, double r, double a,
   if (flag == 0 && !(s > 1e-10 * a)) flag = CLAK_CELL_DEGENERATE;
   double bsnp = nan, se = nan;
   if (flag == 0) {
-    bsnp = r / s;
-    const double var = (flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] / s : 1.0 / s;
-    se = sqrt(var);
+    const double q = 1.0 / s;
+    bsnp = r * q;
+    se = sqrt((flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] * q : q);
   }
   const int64_t o = i + j * out.ldo;
   if (flags & CLAK_OUT_FULL) {
@@ -87,8 +88,9 @@ __device__ __forceinline__ void schur_store_cc(double cc, double r, double a, co
   if (flag == 0 && !(s > 1e-10 * a)) flag = CLAK_CELL_DEGENERATE;
   double bsnp = __builtin_nan(""), se = __builtin_nan("");
   if (flag == 0) {
-    bsnp = r / s;
-    se = sqrt((flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] / s : 1.0 / s);
+    const double q = 1.0 / s;
+    bsnp = r * q;
+    se = sqrt((flags & CLAK_VAR_PAPER) ? tp[PL * PL + PL] * q : q);
   }
   store_snp(out, i + j * out.ldo, bsnp, se, flag, true);
 }
@@ -113,8 +115,9 @@ __device__ __forceinline__ CellResult cell_solve(double cc, double r, double a, 
   o.se = nan;
   o.pv = nan;
   if (o.flag == 0) {
-    o.b = r / s;
-    o.se = sqrt((flags & CLAK_VAR_PAPER) ? s2 / s : 1.0 / s);
+    const double q = 1.0 / s;
+    o.b = r * q;
+    o.se = sqrt((flags & CLAK_VAR_PAPER) ? s2 * q : q);
     if (want_p) o.pv = erfc(fabs(o.b / o.se) * M_SQRT1_2);
   }
   return o;
