@@ -40,9 +40,10 @@ def _eager(plan, blocks):
     torch.cuda.synchronize()
 
 
-@pytest.mark.skip(reason="graph capture of the pipeline ended in a host segmentation fault inside "
-                         "clak_pipeline_create; the cause was not found, the capture path was removed and the "
-                         "pipeline now enqueues eagerly on three streams (see test_two_stream_pipeline_matches_eager)")
+@pytest.mark.skip(reason="graph capture of the pipeline ended in a host segmentation fault in two independent "
+                         "implementations (inside clak_pipeline_create, then inside the first capturing "
+                         "clak_pipeline_launch); the cause was not found, the capture path was removed and the "
+                         "pipeline enqueues eagerly on three streams (see test_two_stream_pipeline_matches_eager)")
 @pytest.mark.parametrize("prec,t", [(1, 1), (1, 7), (0, 1), (0, 7)])
 def test_pipeline_matches_eager_over_replays(prec, t):
     import torch
