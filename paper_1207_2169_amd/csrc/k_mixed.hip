@@ -374,7 +374,13 @@ __device__ __forceinline__ void rot_tile(int64_t np, int64_t nz, int64_t zl, int
   const int64_t ss = snp_stride(PL);
 
   // one column tile at a time (the scheduler is kept from overlapping the
-  // tiles' table reads, which would not fit the registers)
+  // tiles' table reads, which would not fit the registers).  Only the row tile
+  // holding the U^T rows (EPI 1) needs the per-row test between a stored row
+  // and a summed one; every other tile takes the code without it (the same
+  // arithmetic, no divergent branch per element)
+  const bool urow_tile = EPI == 1 && zl <= m0 + BM - 1 && zl + PL >= m0;
+  auto columns = [&](auto with_urows) {
+  constexpr bool UR = decltype(with_urows)::value;
 #pragma unroll
   for (int ct = 0; ct < CT; ++ct) {
     __builtin_amdgcn_sched_barrier(0);
@@ -409,6 +415,8 @@ __device__ __forceinline__ void rot_tile(int64_t np, int64_t nz, int64_t zl, int
         xs[r] = x;
         if (EPI == 0) {
           mx = fmax(mx, fabs(x));
+        } else if (!UR) {
+          pa += Vs[rr] * x * x;
         } else {
           const int64_t row = m0 + rr;
           if (row >= zl && row <= zl + PL)
@@ -429,6 +437,11 @@ __device__ __forceinline__ void rot_tile(int64_t np, int64_t nz, int64_t zl, int
       if ((lane >> 5) == 0) Ps[wr * BN + cl] = sq;
     }
   }
+  };
+  if (urow_tile)
+    columns(std::true_type{});
+  else
+    columns(std::false_type{});
   if (EPI == 1 && !ext) {
     __syncthreads();
     // the WR row slices of the tile combine (fixed order); one partial per
