@@ -303,15 +303,18 @@ clak_status clak_batch_get_info(clak_batch_t batch, int* batched, int64_t* round
 clak_status clak_batch_destroy(clak_batch_t batch);
 
 /* Launch parameters of the mixed path's kernels, all of which leave every
- * result bitwise unchanged (they only change how tiles map to work-groups):
- *   rot_cfg : the rotation's tile configuration, 64-row tiles of 64, 128 or
- *             256 SNPs with two, four or eight waves (1 to 9; 6 to 9, like
- *             the built-in choice, stage their operands by direct
- *             global-to-LDS loads into a ring of three or four K slices, 1
- *             to 5 through registers, one slice ahead);
+ * result bitwise unchanged (they only change how work maps to work-groups):
+ *   rot_cfg : the rotation's tile configuration: 1 to 9, 64-row tiles of 64,
+ *             128 or 256 SNPs with two, four or eight waves (6 to 9 stage
+ *             their operands by direct global-to-LDS loads into a ring of
+ *             three or four K slices, 1 to 5 through registers, one slice
+ *             ahead); 10, the Z-resident kernel (a 32-row slice of Z^T's digit
+ *             planes held in LDS per work-group, genotypes streamed into
+ *             registers; n_pad <= 1024, p_L <= 4, not CLAK_CHOL, else the
+ *             built-in tiles);
  *   rot_rg  : the rotation's XCD row groups (1, 2, 4, 8; the 8 XCDs split into
  *             rot_rg groups of Z^T rows x 8 / rot_rg groups of SNP tiles);
- *   grid_tt : the grid contraction's kernel: 0 the one-pass kernel (p_L <= 3;
+ *   grid_tt : the grid contraction's kernel: 0 the ring kernel (p_L <= 3;
  *             128 SNPs x 32 traits per work-group), 32 or 64 the two-stage
  *             kernel with that many traits per work-group;
  *   grid_xt : with grid_tt = 0, the SNP tiles of an XCD walked together over
@@ -321,7 +324,7 @@ clak_status clak_batch_destroy(clak_batch_t batch);
  * (configuration 6) in single-trait plans whose blocks hold at least 8192
  * SNPs (slower per launch alone, faster in the block pipeline), with one XCD
  * row group under CLAK_CHOL and two otherwise, else 64 x 128 tiles and two
- * row groups; for the grid, the one-pass kernel for p_L <= 3.
+ * row groups; for the grid, the ring kernel for p_L <= 3.
  * Errors: CLAK_E_ARG for other values. */
 clak_status clak_plan_set_tuning(clak_plan_t plan, int rot_cfg, int rot_rg, int grid_tt, int grid_xt);
 
