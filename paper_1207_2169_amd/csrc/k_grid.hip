@@ -1,6 +1,6 @@
 // Grid contraction of the multi-trait CLAK-Eig listing (section 3, the inner
 // loop over (SNP, trait) cells: W_R^T W_L, W_R^T Y_j and W_R^T W_R per cell)
-// in one pass over the individuals, on v_mfma_i32_32x32x32_i8.
+// in one or two passes over the individuals, on v_mfma_i32_32x32x32_i8.
 //
 // For a rotated, centred SNP x and trait j the cell needs p_L + 2 sums over
 // the n eigen indices k (the operand columns built by the trait kernel):
@@ -36,9 +36,11 @@
 // time, so that the work-groups resident on one XCD share those SNP tiles'
 // digits and the trait groups' operand in its L2.
 //
-// Epilogue: per cell the Schur solve in FP64 (as schur_store), then each
-// wave stages its 32 x 32 results per output array in LDS and writes them
-// trait row by trait row, 32 consecutive SNPs per half-wave store.
+// Epilogue: per cell the Schur solve in FP64 (cell_solve, the arithmetic of
+// schur_store), then each wave stages its 32 x 32 results per output array in
+// LDS and writes them trait row by trait row, 32 consecutive SNPs per
+// half-wave store, with the p-value formed from the staged b and SE when it
+// is asked for.
 #include "common.hpp"
 #include "schur.hpp"
 
