@@ -48,15 +48,15 @@ namespace clak {
 
 // The tiles of a cell with p_L = PL <= 3: entries c'_0 .. c'_{p_L-1}, r'
 // (against x) and a (against x o x), p_L + 2 <= 5 tiles, 320 accumulator
-// registers at most.  (Larger p_L would need several passes over K; the
-// two-stage kernel of k_mixed.hip serves them.)
+// registers at most, formed in one or two passes over K.  (Larger p_L would
+// need more passes; the two-stage kernel of k_mixed.hip serves them.)
 template <int PL>
 struct GridTiles {
   static constexpr int NT = PL + 2;
   // LDS fragments per slice at most: 4 planes of each trait operand tile (the
   // SNP tiles' x and x o x planes go to registers)
   static constexpr int FB = 4 * NT;
-  static_assert(PL >= 1 && PL <= 3, "one pass holds p_L <= 3");
+  static_assert(PL >= 1 && PL <= 3, "the ring kernel takes p_L <= 3");
 };
 
 constexpr int GR_SLOT = 52 * 1024;  // a ring slot; after the K loop the epilogue's stages and the parked sums
@@ -183,7 +183,7 @@ __device__ __forceinline__ void grid_tile(const GridArgs& ga, int64_t bid) {
     for (int g = 0; g < 4; ++g) acc[q][g] = (v16i){};
   // the quadratic sums parked between the passes: [r][lane] doubles per wave,
   // waves 0, 1 past byte ASAVE_OFF of slot 0, waves 2, 3 of slot 1 (free of
-  // the second pass's 32 KB slices and of the epilogue's 33.8 KB stages)
+  // the second pass's 16 KB slices and of the epilogue's 33.8 KB stages)
   constexpr int ASAVE_OFF = 36 * 1024;
   static_assert(!TWO || (ASAVE_OFF + 2 * 16 * 64 * 8 <= GR_SLOT && ASAVE_OFF >= 8 * GR_STAGE * 4 &&
                          ASAVE_OFF >= NV * 4 * 1024),
