@@ -50,9 +50,9 @@ __device__ __forceinline__ void ingest_tile(const IngArgs& ia, int64_t bx, int64
   constexpr int NV = PL + 2;  // v, gg, bad
   constexpr int WIN = 16 * ING_WAVES;
   __shared__ double red[ING_WAVES][64][NV + 1];
-  __shared__ __attribute__((aligned(16))) double qs[PL][WIN];
+  __shared__ __attribute__((aligned(1024))) double qs[PL][WIN];
   const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t snp = bx * 64 + lane;
   const int64_t S = ia.S;
   double acc[PL];
@@ -61,8 +61,11 @@ __device__ __forceinline__ void ingest_tile(const IngArgs& ia, int64_t bx, int64
   double gg = 0.0;
   int bad = 0;
   for (int64_t w0 = s0 * WIN; w0 < np; w0 += S * WIN) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < PL * WIN; e += 64 * ING_WAVES) qs[e / WIN][e % WIN] = QL[w0 + e % WIN + (e / WIN) * np];
+    __syncthreads();  // every wave is done with the previous window's Q_L rows
+    // the window's Q_L rows go straight to LDS (row a by wave a % 8, 16 bytes
+    // a lane), so that their latency overlaps that of the genotype loads below
+    for (int a = wid; a < PL; a += ING_WAVES)
+      __builtin_amdgcn_global_load_lds(QL + w0 + a * np + 2 * lane, (lds_ptr_t)&qs[a][0], 16, 0, 0);
     const int64_t i0 = w0 + 16 * wid;
     uint8_t by[16];
 #pragma unroll
@@ -109,7 +112,8 @@ __device__ __forceinline__ void ingest_tile(const IngArgs& ia, int64_t bx, int64
       gg += gd[e] * gd[e];
     }
     if (snp < m_pad) __builtin_memcpy(__builtin_assume_aligned(Gp + kt32(snp, i0, mbp), 16), by, 16);
-    __syncthreads();
+    wait_vm<0>();     // this wave's Q_L rows have landed
+    __syncthreads();  // and every wave's
 #pragma unroll
     for (int a = 0; a < PL; ++a) {
       const double* src = &qs[a][16 * wid];
