@@ -23,6 +23,7 @@ constexpr int64_t TRAIT_PAD = 128;
 constexpr int ROT_CONFIGS = 11;  // tile configurations of the mixed rotation (tunable)
 constexpr int MAX_PL = 16;
 constexpr int ING_MAX_SPLITS = 8;  // individual windows of the ingest are split over at most this many work-groups
+constexpr int ING_WINDOWS_PER_WG = 4;  // and each work-group takes about this many windows
 // int8 digit encoding: a value v with |v| <= s is stored as
 // q = rint(v / s * QMAX), |q| <= QMAX < 2^31, split into four base-256 digits.
 constexpr double QMAX = 2130706432.0;  // 127 * 2^24
@@ -175,12 +176,13 @@ size_t workspace_bytes(const Plan& p, Workspace* carve, char* base);
 size_t slot_bytes(const Plan& p, Slot* carve, char* base);
 
 // Number of work-groups the ingest splits the individuals of one SNP group
-// over: one per 128-individual window, at most ING_MAX_SPLITS.  It depends on
-// n only, so every SNP's statistics are summed in the same order whatever the
-// block split.
+// over: one per ING_WINDOWS_PER_WG 128-individual windows, at most
+// ING_MAX_SPLITS (fewer, longer work-groups hold fewer CUs that the rotation
+// of the previous block could use).  It depends on n only, so every SNP's
+// statistics are summed in the same order whatever the block split.
 inline int ingest_splits(const Plan& p) {
-  const int64_t windows = p.n_pad / 128;
-  return (int)(windows < ING_MAX_SPLITS ? windows : ING_MAX_SPLITS);
+  const int64_t windows = p.n_pad / 128, s = (windows + ING_WINDOWS_PER_WG - 1) / ING_WINDOWS_PER_WG;
+  return (int)(s < ING_MAX_SPLITS ? s : ING_MAX_SPLITS);
 }
 
 constexpr int64_t ZEXT = 64;  // rows of the extra rotation tile (one 64-row tile)
