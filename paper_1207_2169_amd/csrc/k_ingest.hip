@@ -37,7 +37,36 @@ struct IngArgs {
   int8_t* Gp;
   double* ipart;
   int S;
+  const double* Rinv;  // with S = 1 the work-group writes the statistics itself
+  double* sstat;
 };
+
+// The statistics of one SNP from its sums t = (Q_L^T g, g^T g, invalid
+// genotype count):
+//   v = Q_L^T g, gamma = R^{-1} v, ||g - Q_L v|| = sqrt(gg - ||v||^2), and
+//   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
+//   (gg == 0 or ||g - Q_L v||^2 <= 1e-10 gg) or the row pads the block; else 0.
+template <int PL>
+__device__ __forceinline__ void snp_statistics(const double* t, bool pad, const double* __restrict__ Rinv,
+                                               double* st) {
+  double vv = 0.0;
+#pragma unroll
+  for (int a = 0; a < PL; ++a) vv += t[a] * t[a];
+  const double g2 = t[PL];
+  const double res = g2 - vv;
+  const int flag = t[PL + 1] > 0.0 ? 2 : ((pad || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
+#pragma unroll
+  for (int a = 0; a < PL; ++a) {
+    double gam = 0.0;
+#pragma unroll
+    for (int c = a; c < PL; ++c) gam += Rinv[a * PL + c] * t[c];
+    st[a] = flag ? 0.0 : t[a];
+    st[PL + a] = flag ? 0.0 : gam;
+  }
+  st[2 * PL] = flag ? 1.0 : sqrt(res);
+  st[2 * PL + 1] = (double)flag;
+  st[2 * PL + 2] = 0.0;
+}
 
 // Work-group (bx, s0): SNPs 64 bx .., windows s0, s0 + S, ...
 template <int PL, int ALIGN, int KIND>
@@ -132,11 +161,17 @@ __device__ __forceinline__ void ingest_tile(const IngArgs& ia, int64_t bx, int64
   red[wid][lane][PL + 1] = (double)bad;
   __syncthreads();
   if (wid != 0 || snp >= m_pad) return;
+  double t[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    double t = 0.0;
-    for (int w = 0; w < ING_WAVES; ++w) t += red[w][lane][q];
-    ipart[(s0 * NV + q) * mbp + snp] = t;
+    t[q] = 0.0;
+    for (int w = 0; w < ING_WAVES; ++w) t[q] += red[w][lane][q];
+  }
+  if (S == 1) {  // the whole sums: the statistics as pass 2 forms them (0 + t is t)
+    snp_statistics<PL>(t, snp >= m_blk, ia.Rinv, ia.sstat + snp * snp_stride(PL));
+  } else {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) ipart[(s0 * NV + q) * mbp + snp] = t[q];
   }
 }
 
@@ -155,11 +190,9 @@ __global__ void __launch_bounds__(64 * ING_WAVES) k_ingest_batch(BatchArgs<IngAr
   ingest_tile<PL, ALIGN, KIND>(B.a[k], l / B.a[k].S, l % B.a[k].S);
 }
 
-// Pass 2, one thread per SNP: sums the S partials in a fixed order and writes
-//   v = Q_L^T g, gamma = R^{-1} v, ||g - Q_L v|| = sqrt(gg - ||v||^2), and
-//   flag = 2 if a genotype is not in {0, 1, 2}; 1 if g lies in span(X_L)
-//   (gg == 0 or ||g - Q_L v||^2 <= 1e-10 gg); else 0.
-// SNP rows in [m_blk, m_pad) become zero SNPs with flag 1.
+// Pass 2 (S > 1), one thread per SNP: sums the S partials in a fixed order
+// and writes the SNP's statistics (snp_statistics).  SNP rows in
+// [m_blk, m_pad) become zero SNPs with flag 1.
 struct FinArgs {
   int64_t m_blk, m_pad, mbp;
   int S;
@@ -177,31 +210,14 @@ __device__ __forceinline__ void ingest_fin_tile(const FinArgs& fa, int64_t bx) {
   double* __restrict__ sstat = fa.sstat;
   constexpr int NV = PL + 2;
   const int64_t snp = bx * 256 + threadIdx.x;
-  if (snp >= m_pad) return;
+  if (snp >= m_pad || S == 1) return;  // with one split pass 1 wrote the statistics
   double t[NV];
 #pragma unroll
   for (int q = 0; q < NV; ++q) t[q] = 0.0;
   for (int s = 0; s < S; ++s)
 #pragma unroll
     for (int q = 0; q < NV; ++q) t[q] += ipart[(s * NV + q) * mbp + snp];
-  double vv = 0.0;
-#pragma unroll
-  for (int a = 0; a < PL; ++a) vv += t[a] * t[a];
-  const double g2 = t[PL];
-  const double res = g2 - vv;
-  const int flag = t[PL + 1] > 0.0 ? 2 : ((snp >= m_blk || !(g2 > 0.0) || !(res > 1e-10 * g2)) ? 1 : 0);
-  double* st = sstat + snp * snp_stride(PL);
-#pragma unroll
-  for (int a = 0; a < PL; ++a) {
-    double gam = 0.0;
-#pragma unroll
-    for (int c = a; c < PL; ++c) gam += Rinv[a * PL + c] * t[c];
-    st[a] = flag ? 0.0 : t[a];
-    st[PL + a] = flag ? 0.0 : gam;
-  }
-  st[2 * PL] = flag ? 1.0 : sqrt(res);
-  st[2 * PL + 1] = (double)flag;
-  st[2 * PL + 2] = 0.0;
+  snp_statistics<PL>(t, snp >= m_blk, Rinv, sstat + snp * snp_stride(PL));
 }
 
 template <int PL>
@@ -222,7 +238,7 @@ static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const v
   dim3 grid((unsigned)(m_pad / 64), (unsigned)S);
   const Workspace& W = p.ws;
   const dim3 block(64 * ING_WAVES);
-  const IngArgs ia{p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, W.ipart, S};
+  const IngArgs ia{p.n, p.n_pad, m_blk, m_pad, p.mb_pad, d_G, ldg, W.QL, W.Gp, W.ipart, S, W.Rinv, W.sstat};
   if (g_dtype == CLAK_G_F16) {
     k_ingest<PL, 1, 1><<<grid, block, 0, p.stream>>>(ia);
   } else if (g_dtype == CLAK_G_P2) {
@@ -246,8 +262,9 @@ static void ingest_dispatch(const Plan& p, int64_t m_blk, int64_t m_pad, const v
       CLAK_ING(1);
 #undef CLAK_ING
   }
-  k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(
-      FinArgs{m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv, W.sstat});
+  if (S > 1)  // with one split pass 1 has written the statistics
+    k_ingest_fin<PL><<<dim3((unsigned)(m_pad / 256)), 256, 0, p.stream>>>(
+        FinArgs{m_blk, m_pad, p.mb_pad, S, W.ipart, W.Rinv, W.sstat});
 }
 
 template <int PL>
@@ -256,13 +273,15 @@ static hipError_t ingest_batch_pl(const BatchItem* it, int count, int g_dtype, h
   BatchArgs<FinArgs> F{};
   B.count = F.count = count;
   int align = 16;
-  bool words = true;
+  bool words = true, fin = false;  // fin: some plan has more than one split
   for (int k = 0; k < count; ++k) {
     const Plan& p = *it[k].p;
     const Slot& S = p.ws.slot[it[k].slot];
     const int64_t m_pad = roundup(it[k].m_blk, SNP_PAD);
     const int sp = ingest_splits(p);
-    B.a[k] = IngArgs{p.n, p.n_pad, it[k].m_blk, m_pad, p.mb_pad, it[k].G, it[k].ldg, p.ws.QL, S.Gp, S.ipart, sp};
+    B.a[k] = IngArgs{p.n, p.n_pad, it[k].m_blk, m_pad, p.mb_pad, it[k].G, it[k].ldg, p.ws.QL, S.Gp, S.ipart, sp,
+                     p.ws.Rinv, S.sstat};
+    fin = fin || sp > 1;
     F.a[k] = FinArgs{it[k].m_blk, m_pad, p.mb_pad, sp, S.ipart, p.ws.Rinv, S.sstat};
     B.start[k + 1] = B.start[k] + m_pad / 64 * sp;
     F.start[k + 1] = F.start[k] + m_pad / 256;
@@ -284,7 +303,7 @@ static hipError_t ingest_batch_pl(const BatchItem* it, int count, int g_dtype, h
   else
     k_ingest_batch<PL, 1, 0><<<grid, block, 0, st>>>(B);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !fin) return e;
   k_ingest_fin_batch<PL><<<dim3((unsigned)F.start[count]), 256, 0, st>>>(F);
   return hipGetLastError();
 }
