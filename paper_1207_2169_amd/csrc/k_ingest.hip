@@ -11,11 +11,13 @@
 namespace clak {
 
 // Pass 1.  A work-group takes 64 SNPs (one per lane) and the individual
-// windows s, s + S, s + 2S, ... (128 individuals each; blockIdx.y = s); in a
-// window wave w handles individuals [16w, 16w + 16) of every lane's SNP, and
-// the window's 128 rows of Q_L are staged in LDS (read back as wave-uniform
-// broadcasts).  The work-group writes the int8 panel rows of its windows and
-// one partial (Q_L^T g, g^T g, invalid-genotype count) per SNP.
+// windows s, s + S, s + 2S, ... (128 individuals each; blockIdx.y = s; S from
+// ingest_splits, about four windows per work-group); in a window wave w
+// handles individuals [16w, 16w + 16) of every lane's SNP, and the window's
+// 128 rows of Q_L are staged in LDS (read back as wave-uniform broadcasts).
+// The work-group writes the int8 panel rows of its windows and one partial
+// (Q_L^T g, g^T g, invalid-genotype count) per SNP, or, when S = 1, the SNP's
+// statistics themselves (pass 2 is then not launched).
 // ALIGN is the byte alignment shared by G and its leading dimension (u8, and
 // for 2-bit rows whether 4-byte words can be read).  KIND: 0 u8, 1 f16, 2
 // 2-bit codes, four individuals per byte, individual i in bits 2 (i % 4) and
